@@ -1,0 +1,422 @@
+/*
+ * dm_oracle.c -- TEST INFRASTRUCTURE, NOT PART OF THE PRODUCT.
+ *
+ * A plain, slow, obviously-correct FP64 CPU implementation of the
+ * mode-amplitude Langevin time step of Panja, Barkema & van Leeuwen,
+ * "Efficient simulation of semiflexible polymers" (arXiv:1411.3487), and of
+ * the bead-space Euler scheme the paper uses as its default method.
+ *
+ * Only tests/, __graft_entry__.smoke() and bench.py's cpu_baseline leg may
+ * load this file's shared library.  It shares no code, header, table or
+ * constant with the HIP library in paper_1411_3487_amd/; both sides implement
+ * Philox4x32-10 independently from its publication (Salmon, Moraes, Dror &
+ * Shaw, "Parallel random numbers: as easy as 1, 2, 3", SC'11).
+ *
+ * Units are the paper's reduced ones (Sec. 3, Eqs. b3-b5): lengths in d, time
+ * in xi/lambda, noise variance 2 T*.
+ *
+ * Array layout: a chain's positions or mode amplitudes are 3*M doubles,
+ * component-major: x[alpha*M + i], alpha = 0,1,2 (x,y,z), i = bead n or mode
+ * p.  Several chains are stored back to back.
+ *
+ * Readings of the paper taken here (the paper is silent or garbled there):
+ *  - phi_{n,0} = 1/sqrt(M), not sqrt(2/M) as Eq. (c8) prints; only then is
+ *    phi orthogonal, Eq. (c2).  Modes run p = 0..M-1 (M = N+1 beads).
+ *  - The sign of H_p is + dL_c/dR_p, as in Eq. (e1).
+ *  - The decay rate of the coupling integral (f0) is zeta_p of Eq. (e9).
+ *  - p = 0 has zeta = zeta^l = 0 and Delta H_0 = 0: the centre-of-mass mode
+ *    is a random walk with variance 2 T* dtau per component and step.
+ *  - Shear (Eq. btum) enters each mode as R^x_p += gdot*dtau*E_p*R^y_p(old),
+ *    the exact integrating-factor solution of the drift for R^y decaying at
+ *    zeta_p over the step; the x-y noise cross term is neglected.
+ *  - Noise: Philox4x32-10, key = (seed lo, seed hi), counter =
+ *    (index/4, chain, step lo, (step hi << 8) | (component << 4) | tag);
+ *    the four outputs give uniforms (x + 1/2) 2^-32 and two Box-Muller
+ *    pairs, normal j of the block goes to index 4*(index/4) + j.
+ *    Tags: 0 = mode step, 1 = Euler step.
+ *
+ * Parity unpinned: the coupling-integral approximation (f1)-(f2) has no
+ * closed form; it is pinned only through its small-step limit and the
+ * equilibrium statistics the tests check.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "dm_oracle.h"
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10 (Salmon et al. 2011): ten rounds of a multiply-xor         */
+/* bijection on a 128-bit counter, with a Weyl-sequence key schedule.       */
+/* ------------------------------------------------------------------------ */
+void orc_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2],
+                       uint32_t out[4])
+{
+    const uint32_t mul_a = 0xD2511F53u, mul_b = 0xCD9E8D57u;
+    const uint32_t weyl_a = 0x9E3779B9u, weyl_b = 0xBB67AE85u;
+    uint32_t c0 = ctr_in[0], c1 = ctr_in[1], c2 = ctr_in[2], c3 = ctr_in[3];
+    uint32_t k0 = key_in[0], k1 = key_in[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += weyl_a;
+            k1 += weyl_b;
+        }
+        uint64_t pa = (uint64_t)mul_a * (uint64_t)c0;
+        uint64_t pb = (uint64_t)mul_b * (uint64_t)c2;
+        uint32_t pa_hi = (uint32_t)(pa >> 32), pa_lo = (uint32_t)pa;
+        uint32_t pb_hi = (uint32_t)(pb >> 32), pb_lo = (uint32_t)pb;
+        uint32_t n0 = pb_hi ^ c1 ^ k0;
+        uint32_t n1 = pb_lo;
+        uint32_t n2 = pa_hi ^ c3 ^ k1;
+        uint32_t n3 = pa_lo;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* Four standard normals for the noise block (index/4) of one component. */
+void orc_gauss4(uint64_t seed, uint32_t block, uint32_t chain, int64_t step,
+                uint32_t comp, uint32_t tag, double z[4])
+{
+    uint64_t k = (uint64_t)step;
+    uint32_t ctr[4] = {block, chain, (uint32_t)k,
+                       (uint32_t)((k >> 32) << 8) | (comp << 4) | tag};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t x[4];
+    orc_philox4x32_10(ctr, key, x);
+    const double two_m32 = 1.0 / 4294967296.0;
+    const double two_pi = 6.283185307179586476925286766559;
+    double u[4];
+    for (int j = 0; j < 4; ++j) u[j] = ((double)x[j] + 0.5) * two_m32;
+    double ra = sqrt(-2.0 * log(u[0])), rb = sqrt(-2.0 * log(u[2]));
+    z[0] = ra * cos(two_pi * u[1]);
+    z[1] = ra * sin(two_pi * u[1]);
+    z[2] = rb * cos(two_pi * u[3]);
+    z[3] = rb * sin(two_pi * u[3]);
+}
+
+double orc_normal(uint64_t seed, uint32_t index, uint32_t chain, int64_t step,
+                  uint32_t comp, uint32_t tag)
+{
+    double z[4];
+    orc_gauss4(seed, index / 4u, chain, step, comp, tag, z);
+    return z[index % 4u];
+}
+
+/* ------------------------------------------------------------------------ */
+/* Model parameters, Sec. 2 (Eqs. a2, a3) and Sec. 7b (Eq. g2).             */
+/* ------------------------------------------------------------------------ */
+void orc_reduced_params(double lambda, double kappa, double kT, double a,
+                        double xi, double *T_star, double *nu, double *b,
+                        double *d, double *time_unit)
+{
+    /* nu = kappa/lambda; b = 1/(1-2 nu) and a = b d (Eq. a3);
+       T* = kT/(lambda d^2); t = (xi/lambda) tau (Sec. 3). */
+    double n_ = kappa / lambda;
+    double b_ = 1.0 / (1.0 - 2.0 * n_);
+    double d_ = a / b_;
+    *nu = n_;
+    *b = b_;
+    *d = d_;
+    *T_star = kT / (lambda * d_ * d_);
+    *time_unit = xi / lambda;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Mode tables for one chain length: Eqs. (c8), (c9), (e9), (d3), (d6),     */
+/* (f2).  phi is row-major phi[n*M + p].                                    */
+/* ------------------------------------------------------------------------ */
+void orc_tables(int M, double nu, double T_star, double dtau, double *phi,
+                double *zeta_l, double *zeta, double *E, double *C,
+                double *W)
+{
+    const double pi = 3.141592653589793238462643383279502884;
+    for (int n = 0; n < M; ++n)
+        for (int p = 0; p < M; ++p) {
+            double norm = (p == 0) ? sqrt(1.0 / M) : sqrt(2.0 / M);
+            phi[n * M + p] = norm * cos(p * (n + 0.5) * pi / M);
+        }
+    for (int p = 0; p < M; ++p) {
+        double cp = cos(p * pi / M);
+        double sp = sin(p * pi / (2.0 * M));
+        /* Eq. (c9): longitudinal (Rouse) eigenvalue. */
+        double zl = 2.0 * (1.0 - cp) * (1.0 - 2.0 * nu * cp);
+        /* Eq. (e9): the decay rate left after moving the linear part of the
+           coupling, (1-2nu) [2 sin(p pi / 2M)]^2 R_p, to the left side. */
+        double z = zl - (1.0 - 2.0 * nu) * (2.0 * sp) * (2.0 * sp);
+        if (p == 0) {
+            zl = 0.0;
+            z = 0.0;
+        }
+        zeta_l[p] = zl;
+        zeta[p] = z;
+        /* Eq. (d3): exact decay of the free mode over one step. */
+        E[p] = exp(-z * dtau);
+        /* Eq. (f2): [exp(-z dtau) - exp(-zl dtau)] / (zl - z), written as
+           exp(-z dtau) * [1 - exp(-(zl-z) dtau)] / (zl - z) with expm1;
+           its zl -> z limit is dtau exp(-z dtau) (Eq. f3 for small p). */
+        double dz = zl - z;
+        C[p] = (dz > 0.0) ? -E[p] * expm1(-dz * dtau) / dz : dtau * E[p];
+        /* Eq. (d6): variance T* [1 - exp(-2 z dtau)] / z, limit 2 T* dtau. */
+        W[p] = (z > 0.0) ? sqrt(-T_star * expm1(-2.0 * z * dtau) / z)
+                         : sqrt(2.0 * T_star * dtau);
+    }
+}
+
+/* Eq. (c1): R_p = sum_n r_n phi_{n,p}. */
+void orc_modes_from_positions(int M, const double *phi, const double *pos,
+                              double *R)
+{
+    for (int a = 0; a < 3; ++a)
+        for (int p = 0; p < M; ++p) {
+            double s = 0.0;
+            for (int n = 0; n < M; ++n) s += pos[a * M + n] * phi[n * M + p];
+            R[a * M + p] = s;
+        }
+}
+
+/* Eq. (c1): r_n = sum_p phi_{n,p} R_p, over p >= p_first. */
+static void positions_from_modes(int M, const double *phi, const double *R,
+                                 int p_first, double *pos)
+{
+    for (int a = 0; a < 3; ++a)
+        for (int n = 0; n < M; ++n) {
+            double s = 0.0;
+            for (int p = p_first; p < M; ++p)
+                s += phi[n * M + p] * R[a * M + p];
+            pos[a * M + n] = s;
+        }
+}
+
+void orc_positions_from_modes(int M, const double *phi, const double *R,
+                              double *pos)
+{
+    positions_from_modes(M, phi, R, 0, pos);
+}
+
+/* Nonlinear part of the coupling, Eqs. (e4), (e11), via the bead force:
+   u_n = r_n - r_{n-1}; g_n = u_n (1/|u_n| - (1-2nu)) for bonds n = 1..M-1;
+   F_n = g_n - g_{n+1} with g_0 = g_M = 0; Delta H_p = sum_n phi_{n,p} F_n.
+   r are positions without the p = 0 mode (forces are translation
+   invariant).  dH[a*M + p], dH_0 is returned as computed. */
+static void delta_h_from_positions(int M, const double *phi, double nu,
+                                   const double *r, double *g, double *F,
+                                   double *dH)
+{
+    const double lin = 1.0 - 2.0 * nu;
+    for (int n = 1; n < M; ++n) {
+        double u[3], l2 = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            u[a] = r[a * M + n] - r[a * M + n - 1];
+            l2 += u[a] * u[a];
+        }
+        double l = sqrt(l2);
+        for (int a = 0; a < 3; ++a) g[a * M + n] = u[a] * (1.0 / l - lin);
+    }
+    for (int a = 0; a < 3; ++a) {
+        g[a * M + 0] = 0.0; /* g_0 = 0; g_M handled below */
+        for (int n = 0; n < M; ++n) {
+            double gn = (n >= 1) ? g[a * M + n] : 0.0;
+            double gn1 = (n + 1 <= M - 1) ? g[a * M + n + 1] : 0.0;
+            F[a * M + n] = gn - gn1;
+        }
+        for (int p = 0; p < M; ++p) {
+            double s = 0.0;
+            for (int n = 0; n < M; ++n) s += phi[n * M + p] * F[a * M + n];
+            dH[a * M + p] = s;
+        }
+    }
+}
+
+void orc_delta_h(int M, double nu, const double *R, double *dH)
+{
+    double *phi = malloc(sizeof(double) * M * M);
+    double *zl = malloc(sizeof(double) * M), *z = malloc(sizeof(double) * M);
+    double *E = malloc(sizeof(double) * M), *C = malloc(sizeof(double) * M);
+    double *W = malloc(sizeof(double) * M);
+    double *r = malloc(sizeof(double) * 3 * M), *g = malloc(sizeof(double) * 3 * M);
+    double *F = malloc(sizeof(double) * 3 * M);
+    orc_tables(M, nu, 1.0, 1.0, phi, zl, z, E, C, W);
+    positions_from_modes(M, phi, R, 1, r);
+    delta_h_from_positions(M, phi, nu, r, g, F, dH);
+    free(phi); free(zl); free(z); free(E); free(C); free(W);
+    free(r); free(g); free(F);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Mode step, Sec. 4: Eq. (e10) integrated with the integrating factor of   */
+/* Eq. (d3), noise of Eq. (d6), coupling integral of Eq. (f2), and the      */
+/* shear drift of Eq. (btum).                                               */
+/* ------------------------------------------------------------------------ */
+void orc_step_modes(int M, int n_chains, const uint32_t *chain_id, double *R,
+                    double nu, double T_star, double dtau, double gamma_dot,
+                    int nonlinear, uint64_t seed, int64_t step0,
+                    int64_t n_steps)
+{
+    double *phi = malloc(sizeof(double) * M * M);
+    double *zl = malloc(sizeof(double) * M), *z = malloc(sizeof(double) * M);
+    double *E = malloc(sizeof(double) * M), *C = malloc(sizeof(double) * M);
+    double *W = malloc(sizeof(double) * M);
+    orc_tables(M, nu, T_star, dtau, phi, zl, z, E, C, W);
+
+#pragma omp parallel
+    {
+        double *r = malloc(sizeof(double) * 3 * M);
+        double *g = malloc(sizeof(double) * 3 * M);
+        double *F = malloc(sizeof(double) * 3 * M);
+        double *dH = malloc(sizeof(double) * 3 * M);
+#pragma omp for schedule(dynamic, 1)
+        for (int c = 0; c < n_chains; ++c) {
+            double *Rc = R + (size_t)c * 3 * M;
+            for (int64_t k = step0; k < step0 + n_steps; ++k) {
+                if (nonlinear) {
+                    positions_from_modes(M, phi, Rc, 1, r);
+                    delta_h_from_positions(M, phi, nu, r, g, F, dH);
+                }
+                for (int p = 0; p < M; ++p) {
+                    double ry_old = Rc[1 * M + p];
+                    for (int a = 0; a < 3; ++a) {
+                        double eta = orc_normal(seed, (uint32_t)p, chain_id[c],
+                                                k, (uint32_t)a, 0u);
+                        double v = E[p] * Rc[a * M + p] + W[p] * eta;
+                        if (nonlinear && p > 0) v += C[p] * dH[a * M + p];
+                        Rc[a * M + p] = v;
+                    }
+                    Rc[0 * M + p] += gamma_dot * dtau * E[p] * ry_old;
+                }
+            }
+        }
+        free(r); free(g); free(F); free(dH);
+    }
+    free(phi); free(zl); free(z); free(E); free(C); free(W);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Bead-space Euler step of Eqs. (b3)-(b5) (the paper's default method),    */
+/* with the shear drift of Eq. (btum).  pos is 3*M per chain.               */
+/*   h_n = dH'/du_n = (|u_n| - 1) u_n/|u_n| - nu (u_{n-1} + u_{n+1}),        */
+/*   -dH'/dr_n = h_{n+1} - h_n, with u_0 = u_M = 0 and h_0 = h_M = 0.       */
+/* ------------------------------------------------------------------------ */
+void orc_bead_force(int M, double nu, const double *pos, double *f)
+{
+    double *u = malloc(sizeof(double) * 3 * (M + 1));
+    double *h = malloc(sizeof(double) * 3 * (M + 1));
+    for (int a = 0; a < 3; ++a) {
+        u[a * (M + 1) + 0] = 0.0;
+        u[a * (M + 1) + M] = 0.0;
+        for (int n = 1; n < M; ++n)
+            u[a * (M + 1) + n] = pos[a * M + n] - pos[a * M + n - 1];
+    }
+    for (int n = 0; n <= M; ++n) {
+        if (n == 0 || n == M) {
+            for (int a = 0; a < 3; ++a) h[a * (M + 1) + n] = 0.0;
+            continue;
+        }
+        double l2 = 0.0;
+        for (int a = 0; a < 3; ++a) l2 += u[a * (M + 1) + n] * u[a * (M + 1) + n];
+        double l = sqrt(l2);
+        for (int a = 0; a < 3; ++a) {
+            double un = u[a * (M + 1) + n];
+            double nb = u[a * (M + 1) + n - 1] + u[a * (M + 1) + n + 1];
+            h[a * (M + 1) + n] = (l - 1.0) * un / l - nu * nb;
+        }
+    }
+    for (int a = 0; a < 3; ++a)
+        for (int n = 0; n < M; ++n)
+            f[a * M + n] = h[a * (M + 1) + n + 1] - h[a * (M + 1) + n];
+    free(u);
+    free(h);
+}
+
+void orc_step_euler(int M, int n_chains, const uint32_t *chain_id, double *pos,
+                    double nu, double T_star, double dtau, double gamma_dot,
+                    uint64_t seed, int64_t step0, int64_t n_steps)
+{
+    const double amp = sqrt(2.0 * T_star * dtau);
+#pragma omp parallel
+    {
+        double *f = malloc(sizeof(double) * 3 * M);
+#pragma omp for schedule(dynamic, 1)
+        for (int c = 0; c < n_chains; ++c) {
+            double *x = pos + (size_t)c * 3 * M;
+            for (int64_t k = step0; k < step0 + n_steps; ++k) {
+                orc_bead_force(M, nu, x, f);
+                for (int n = 0; n < M; ++n) {
+                    double y_old = x[1 * M + n];
+                    for (int a = 0; a < 3; ++a) {
+                        double eta = orc_normal(seed, (uint32_t)n, chain_id[c],
+                                                k, (uint32_t)a, 1u);
+                        x[a * M + n] += dtau * f[a * M + n] + amp * eta;
+                    }
+                    x[0 * M + n] += gamma_dot * dtau * y_old;
+                }
+            }
+        }
+        free(f);
+    }
+}
+
+/* Reduced Hamiltonian H' = H/(lambda d^2) of Eq. (a2) times T*:
+   H' = 1/2 sum_n (|u_n| - 1)^2 - nu sum_n u_n . u_{n+1}. */
+double orc_energy(int M, double nu, const double *pos)
+{
+    double e = 0.0;
+    double up[3] = {0, 0, 0};
+    for (int n = 1; n < M; ++n) {
+        double u[3], l2 = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            u[a] = pos[a * M + n] - pos[a * M + n - 1];
+            l2 += u[a] * u[a];
+        }
+        double l = sqrt(l2);
+        e += 0.5 * (l - 1.0) * (l - 1.0);
+        if (n >= 2) e -= nu * (u[0] * up[0] + u[1] * up[1] + u[2] * up[2]);
+        for (int a = 0; a < 3; ++a) up[a] = u[a];
+    }
+    return e;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Observables of Sec. 5b: per chain, from positions (3*M).                 */
+/* out[0] mean bond length, out[1] |L|^2 with L = r_{M-1} - r_0,            */
+/* out[2..4] L, out[5..7] centre of mass, out[8..10] middle bond            */
+/* u_m (m = M/2), out[11..13] r_mid - r_cm (mid = (M-1)/2),                 */
+/* out[14] x extent max x - min x, out[15] mean squared bond length.        */
+/* ------------------------------------------------------------------------ */
+void orc_chain_observables(int M, const double *pos, double *out)
+{
+    double lsum = 0.0, l2sum = 0.0;
+    for (int n = 1; n < M; ++n) {
+        double l2 = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            double u = pos[a * M + n] - pos[a * M + n - 1];
+            l2 += u * u;
+        }
+        lsum += sqrt(l2);
+        l2sum += l2;
+    }
+    out[0] = lsum / (M - 1);
+    double L[3], cm[3];
+    for (int a = 0; a < 3; ++a) {
+        L[a] = pos[a * M + M - 1] - pos[a * M + 0];
+        double s = 0.0;
+        for (int n = 0; n < M; ++n) s += pos[a * M + n];
+        cm[a] = s / M;
+    }
+    out[1] = L[0] * L[0] + L[1] * L[1] + L[2] * L[2];
+    int m = M / 2, mid = (M - 1) / 2;
+    for (int a = 0; a < 3; ++a) {
+        out[2 + a] = L[a];
+        out[5 + a] = cm[a];
+        out[8 + a] = pos[a * M + m] - pos[a * M + m - 1];
+        out[11 + a] = pos[a * M + mid] - cm[a];
+    }
+    double xmin = pos[0], xmax = pos[0];
+    for (int n = 1; n < M; ++n) {
+        if (pos[n] < xmin) xmin = pos[n];
+        if (pos[n] > xmax) xmax = pos[n];
+    }
+    out[14] = xmax - xmin;
+    out[15] = l2sum / (M - 1);
+}

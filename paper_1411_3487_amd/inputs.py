@@ -1,0 +1,59 @@
+"""Seeded synthetic inputs shared by the tests, the bench and the smoke run.
+
+This module holds none of the method's arithmetic: it only draws initial
+conformations and chain lengths with numpy's default generator, so that the
+HIP library and the CPU oracle can be started from identical inputs.
+
+Recipe (the paper's workloads are single dsDNA chains of 64-512 basepairs,
+one bead per basepair, Sec. 2a and Sec. 5b):
+  * a chain of M beads starts straight, with consecutive beads ``spacing``
+    apart (the mean bond length a = b d, i.e. b in reduced units), along x
+    or along a direction drawn uniformly on the unit sphere;
+  * every bead coordinate gets Gaussian jitter of standard deviation
+    ``jitter * spacing`` (0.01 a by default);
+  * uneven ensembles draw each chain's length uniformly from a list.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def straight_chains(n_chains: int, M: int, spacing: float, seed: int,
+                    random_orientation: bool = True,
+                    jitter: float = 0.01) -> np.ndarray:
+    """Positions (n_chains, 3, M) float64 in units of d."""
+    rng = np.random.default_rng(seed)
+    if random_orientation:
+        cos_t = rng.uniform(-1.0, 1.0, n_chains)
+        ang = rng.uniform(0.0, 2.0 * np.pi, n_chains)
+        sin_t = np.sqrt(np.maximum(0.0, 1.0 - cos_t * cos_t))
+        e = np.stack([sin_t * np.cos(ang), sin_t * np.sin(ang), cos_t], axis=1)
+    else:
+        e = np.tile(np.array([1.0, 0.0, 0.0]), (n_chains, 1))
+    n = np.arange(M, dtype=np.float64) * spacing
+    pos = e[:, :, None] * n[None, None, :]
+    pos += jitter * spacing * rng.standard_normal((n_chains, 3, M))
+    return pos
+
+
+def mixed_lengths(n_chains: int, lengths, seed: int) -> np.ndarray:
+    """Chain lengths (beads) drawn uniformly from ``lengths``, int32."""
+    rng = np.random.default_rng(seed)
+    lengths = np.asarray(lengths, dtype=np.int32)
+    return lengths[rng.integers(0, len(lengths), n_chains)].astype(np.int32)
+
+
+def mixed_chains(beads: np.ndarray, spacing: float, seed: int,
+                 jitter: float = 0.01) -> list:
+    """One (3, M_c) array per chain for an uneven ensemble."""
+    rng = np.random.default_rng(seed + 1000003)
+    out = []
+    for M in beads:
+        cos_t = rng.uniform(-1.0, 1.0)
+        ang = rng.uniform(0.0, 2.0 * np.pi)
+        sin_t = np.sqrt(max(0.0, 1.0 - cos_t * cos_t))
+        e = np.array([sin_t * np.cos(ang), sin_t * np.sin(ang), cos_t])
+        n = np.arange(int(M), dtype=np.float64) * spacing
+        p = e[:, None] * n[None, :] + jitter * spacing * rng.standard_normal((3, int(M)))
+        out.append(p)
+    return out

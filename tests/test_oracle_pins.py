@@ -1,0 +1,491 @@
+"""Pins of the FP64 CPU oracle against what the paper and mathematics fix.
+
+Each test checks the oracle against something other than itself: a library
+routine, a numerical derivative of the energy, a quadrature, a closed form, a
+linear solve, or an independent implementation (rocRAND's Philox engine).
+Equation labels are those of arXiv:1411.3487.
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+import pytest
+import scipy.fft
+import scipy.integrate
+import scipy.stats
+
+import oracle
+
+NU = 0.35        # dsDNA, Sec. 2a
+TSTAR = 0.034    # dsDNA, Sec. 2a
+B_FAC = 1.0 / (1.0 - 2.0 * NU)   # Eq. (a3)
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+# ---------------------------------------------------------------- helpers
+def energy_np(pos, nu):
+    """Reduced Hamiltonian of Eq. (a2) times T*, written from its definition."""
+    u = np.diff(pos, axis=-1)                     # bonds u_n = r_n - r_{n-1}
+    ell = np.sqrt((u * u).sum(axis=0))
+    bend = (u[:, :-1] * u[:, 1:]).sum()
+    return 0.5 * ((ell - 1.0) ** 2).sum() - nu * bend
+
+
+def dct_phi(M):
+    """phi[n, p] from scipy's orthonormal DCT-II: R = phi^T r."""
+    D = scipy.fft.dct(np.eye(M), type=2, norm="ortho", axis=0)   # D[p, n]
+    return D.T
+
+
+def near_straight(M, seed, amp=0.05):
+    rng = np.random.default_rng(seed)
+    pos = np.zeros((3, M))
+    pos[0] = np.arange(M) * B_FAC
+    return pos + amp * B_FAC * rng.standard_normal((3, M))
+
+
+# ---------------------------------------------------------------- Philox
+def _rocrand_lib(tmp_path_factory):
+    src = os.path.join(HERE, "pins", "rocrand_philox_ref.cpp")
+    out = str(tmp_path_factory.mktemp("rr") / "librr.so")
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    if not os.path.exists(hipcc):
+        pytest.skip("hipcc / rocRAND headers not available")
+    subprocess.run([hipcc, "-O1", "-fPIC", "-shared", "--offload-arch=gfx950",
+                    "-o", out, src], check=True, capture_output=True)
+    lib = ctypes.CDLL(out)
+    lib.rr_philox_block.argtypes = [ctypes.c_uint64] * 3 + [ctypes.c_void_p]
+    return lib
+
+
+def test_philox_matches_rocrand_engine(tmp_path_factory):
+    """Philox4x32-10 bit-exact against rocRAND's independent engine."""
+    lib = _rocrand_lib(tmp_path_factory)
+    rng = np.random.default_rng(123)
+    for i in range(2000):
+        seed = int(rng.integers(0, 2**63)) if i else 0
+        ctr = rng.integers(0, 2**32, 4, dtype=np.uint64)
+        ctr[1] &= (1 << 29) - 1          # keep 4 * (c0 | c1 << 32) below 2^64
+        if i == 0:
+            ctr[:] = 0
+        k = int(ctr[0]) | (int(ctr[1]) << 32)
+        s = int(ctr[2]) | (int(ctr[3]) << 32)
+        ref = np.zeros(4, dtype=np.uint32)
+        lib.rr_philox_block(seed, k, s, ref.ctypes.data)
+        key = [seed & 0xFFFFFFFF, seed >> 32]
+        got = oracle.philox4x32_10(ctr.astype(np.uint32), key)
+        assert np.array_equal(got, ref), (i, seed, ctr, got, ref)
+
+
+def test_gauss_noise_is_standard_normal():
+    """Box-Muller output: N(0,1) marginals, no correlation within a block or
+    across neighbouring counters (chain, step, component)."""
+    z = []
+    for chain in range(40):
+        for step in range(50):
+            for comp in range(3):
+                z.append(oracle.gauss4(7, 3, chain, step, comp, 0))
+    z = np.array(z)              # (6000, 4)
+    flat = z.ravel()
+    n = flat.size
+    assert abs(flat.mean()) < 5.0 / np.sqrt(n)
+    assert abs(flat.var() - 1.0) < 5.0 * np.sqrt(2.0 / n)
+    assert abs(scipy.stats.kurtosis(flat, fisher=False) - 3.0) < 0.15
+    assert scipy.stats.kstest(flat, "norm").pvalue > 1e-3
+    c = np.corrcoef(z.T)
+    assert np.max(np.abs(c - np.eye(4))) < 5.0 / np.sqrt(z.shape[0])
+    # consecutive counters (step k vs k+1) are uncorrelated
+    zz = z.reshape(40, 50, 3, 4)
+    r = np.corrcoef(zz[:, :-1].ravel(), zz[:, 1:].ravel())[0, 1]
+    assert abs(r) < 5.0 / np.sqrt(zz[:, :-1].size)
+
+
+def test_normal_index_maps_into_blocks():
+    """normal(index) is element index % 4 of block index / 4."""
+    blk = oracle.gauss4(11, 5, 2, 9, 1, 1)
+    for j in range(4):
+        assert oracle.normal(11, 20 + j, 2, 9, 1, 1) == blk[j]
+
+
+# ---------------------------------------------------------------- tables
+@pytest.mark.parametrize("M", [2, 3, 8, 64, 255, 256])
+def test_phi_is_orthonormal_dct2(M):
+    """Eq. (c8) with phi_{n,0} = 1/sqrt(M) is the orthonormal DCT-II (c2)."""
+    t = oracle.tables(M, NU, TSTAR, 1.0)
+    assert np.allclose(t["phi"], dct_phi(M), atol=5e-14, rtol=0)
+    assert np.allclose(t["phi"].T @ t["phi"], np.eye(M), atol=1e-13)
+
+
+@pytest.mark.parametrize("M", [2, 5, 16, 64])
+def test_zeta_l_diagonalises_quadratic_energy(M):
+    """Eqs. (c6), (c9), (c10): phi^T A phi = diag(zeta^l) for the quadratic
+    form A of H* = 1/2 sum |u_n|^2 - nu sum u_n . u_{n+1}."""
+    Dm = np.diff(np.eye(M), axis=0)              # (M-1, M): u = Dm r
+    S = np.eye(M - 1, k=1)                        # u_{n+1} picked from u_n
+    A = Dm.T @ Dm - NU * (Dm.T @ (S + S.T) @ Dm)
+    phi = dct_phi(M)
+    t = oracle.tables(M, NU, TSTAR, 1.0)
+    assert np.allclose(phi.T @ A @ phi, np.diag(t["zeta_l"]), atol=1e-12)
+
+
+@pytest.mark.parametrize("M", [3, 16, 64, 512])
+def test_bond_modes_orthogonality_and_zeta(M):
+    """Eq. (e6): chi = phi_n - phi_{n-1} has chi^T chi = diag([2 sin(p pi/2M)]^2);
+    Eq. (e9) then equals 16 nu sin^4(p pi / 2M) (algebra of c9)."""
+    phi = dct_phi(M)
+    chi = np.diff(phi, axis=0)
+    s = np.sin(np.arange(M) * np.pi / (2 * M))
+    assert np.allclose(chi.T @ chi, np.diag(4 * s * s), atol=1e-12)
+    t = oracle.tables(M, NU, TSTAR, 1.0)
+    # (e9) subtracts two O(zeta^l) terms built from 1 - cos(p pi/M): the
+    # rounding is absolute, a few eps, not relative to the small zeta_p
+    err = np.abs(t["zeta"] - 16 * NU * s ** 4)
+    assert np.all(err <= 1e-12 * 16 * NU * s ** 4 + 2e-15)
+
+
+@pytest.mark.parametrize("M,dtau", [(8, 0.1), (64, 10.0), (512, 100.0), (256, 0.01)])
+def test_step_coefficients_by_quadrature(M, dtau):
+    """E, C, W of Eqs. (d3), (f2), (d6) against direct quadrature of the
+    integrals (d4), (d5) with the decay assumption (f1)."""
+    t = oracle.tables(M, NU, TSTAR, dtau)
+    for p in [1, 2, M // 3, M - 1]:
+        z, zl = t["zeta"][p], t["zeta_l"][p]
+        assert t["E"][p] == pytest.approx(np.exp(-z * dtau), rel=1e-14)
+        c_ref = scipy.integrate.quad(lambda s: np.exp(-z * (dtau - s)) * np.exp(-zl * s),
+                                     0, dtau, epsabs=0, epsrel=1e-12, limit=200)[0]
+        w2_ref = scipy.integrate.quad(lambda s: 2 * TSTAR * np.exp(-2 * z * (dtau - s)),
+                                      0, dtau, epsabs=0, epsrel=1e-12, limit=200)[0]
+        assert t["C"][p] == pytest.approx(c_ref, rel=1e-9, abs=1e-300)
+        assert t["W"][p] ** 2 == pytest.approx(w2_ref, rel=1e-9)
+    # p = 0: free diffusion, variance 2 T* dtau; E_0 = 1
+    assert t["W"][0] ** 2 == pytest.approx(2 * TSTAR * dtau, rel=1e-14)
+    assert t["E"][0] == 1.0
+
+
+def test_time_step_table_in_physical_units():
+    """Table 2: dtau_max 10/50/100/100 <-> dt_max 1.59/7.96/15.9/15.9 ps,
+    via Eq. (g2) with a^2 xi / kT = 52.0 ps (Sec. 7b)."""
+    rows = np.loadtxt(os.path.join(HERE, "golden", "table2_time_steps.txt"))
+    kT = 4.089                       # pN nm at 23 C (Sec. 7b)
+    a = 0.33                         # nm (Sec. 2a)
+    xi = 52.0 * kT / a ** 2          # pN ps / nm, so that a^2 xi/kT = 52.0 ps
+    d = a / B_FAC
+    lam = kT / (TSTAR * d * d)
+    p = oracle.reduced_params(lam, NU * lam, kT, a, xi)
+    assert p["T_star"] == pytest.approx(TSTAR, rel=1e-14)
+    assert p["nu"] == pytest.approx(NU, rel=1e-14)
+    for _, dtau, dt_ps in rows:
+        assert dtau * p["time_unit"] == pytest.approx(dt_ps, rel=5e-3)
+
+
+# ---------------------------------------------------------------- forces
+@pytest.mark.parametrize("M", [2, 3, 9, 32])
+def test_energy_matches_definition(M):
+    pos = near_straight(M, M)
+    assert oracle.energy(pos, NU) == pytest.approx(energy_np(pos, NU), rel=1e-13)
+
+
+@pytest.mark.parametrize("M", [2, 3, 9, 32])
+def test_delta_h_is_exact_mode_force(M):
+    """Eq. (e10) is exact: -dH'/dR_p = -zeta_p R_p + Delta H_p for any
+    configuration; checked by complex-step derivatives of the energy (a2)."""
+    pos = near_straight(M, 100 + M, amp=0.2)
+    phi = dct_phi(M)
+    R = phi.T @ pos.T                    # (M, 3)
+    R = R.T.copy()                       # (3, M)
+    dH = oracle.delta_h(R, NU)
+    z = oracle.tables(M, NU, TSTAR, 1.0)["zeta"]
+    h = 1e-30                    # complex-step derivative, exact to rounding
+    for a in range(3):
+        for p in range(1, M):
+            Rc = R.astype(complex)
+            Rc[a, p] += 1j * h
+            fd = -energy_np((phi @ Rc.T).T, NU).imag / h
+            assert fd == pytest.approx(-z[p] * R[a, p] + dH[a, p], abs=1e-12), (a, p)
+    assert np.allclose(dH[:, 0], 0.0, atol=1e-12)     # chi_{n,0} = 0
+
+
+@pytest.mark.parametrize("M", [2, 3, 9, 32])
+def test_bead_force_is_energy_gradient(M):
+    """Euler force of Eq. (b3): -dH'/dr_n by complex-step derivatives of (a2)."""
+    pos = near_straight(M, 200 + M, amp=0.2)
+    f = oracle.bead_force(pos, NU)
+    h = 1e-30                    # complex-step derivative, exact to rounding
+    for a in range(3):
+        for n in range(M):
+            pc = pos.astype(complex)
+            pc[a, n] += 1j * h
+            fd = -energy_np(pc, NU).imag / h
+            assert f[a, n] == pytest.approx(fd, abs=1e-12)
+    assert np.allclose(f.sum(axis=1), 0.0, atol=1e-12)  # no net force
+
+
+# ---------------------------------------------------------------- dynamics
+def test_free_mode_step_is_exact_ou_transition():
+    """With the coupling off each mode is an OU process (Sec. 4, Eqs. d3, d6):
+    one step from a fixed state has mean E_p R_p and variance W_p^2."""
+    M, B, dtau = 8, 6000, 3.0
+    R0 = np.tile(near_straight(M, 1), (1, 1))
+    R0 = (dct_phi(M).T @ R0.T).T
+    Rs = np.repeat(R0[None], B, axis=0)
+    out = oracle.step_modes(Rs, NU, TSTAR, dtau, 1, seed=5, nonlinear=False)
+    t = oracle.tables(M, NU, TSTAR, dtau)
+    mean = out.mean(axis=0)
+    var = out.var(axis=0)
+    for p in range(M):
+        se = t["W"][p] / np.sqrt(B)
+        assert np.all(np.abs(mean[:, p] - t["E"][p] * R0[:, p]) < 5 * se)
+        assert np.all(np.abs(var[:, p] / t["W"][p] ** 2 - 1) < 5 * np.sqrt(2.0 / B))
+
+
+def test_centre_of_mass_diffuses_with_D_equal_T_over_M():
+    """Sec. 7b: free-draining D = kT/(M xi), i.e. T*/M in reduced units;
+    <|dr_cm|^2> = 6 D tau for any dtau because Delta H_0 = 0."""
+    M, B, dtau, K = 16, 800, 5.0, 40
+    pos = np.stack([near_straight(M, s) for s in range(B)])
+    R = np.einsum("np,ban->bap", dct_phi(M), pos)
+    out = oracle.step_modes(R, NU, TSTAR, dtau, K, seed=9)
+    dcm = (out[:, :, 0] - R[:, :, 0]) / np.sqrt(M)
+    msd = (dcm ** 2).sum(axis=1)
+    expect = 6 * (TSTAR / M) * K * dtau
+    assert msd.mean() == pytest.approx(expect, rel=5 * np.sqrt(2.0 / (3 * B)))
+
+
+def _relax(M, scheme, dtau, n_steps):
+    pos = near_straight(M, 3, amp=0.02)
+    if scheme == "euler":
+        return oracle.step_euler(pos[None], NU, 0.0, dtau, n_steps)[0]
+    R = (dct_phi(M).T @ pos.T).T[None]
+    R = oracle.step_modes(R, NU, 0.0, dtau, n_steps)
+    return oracle.positions_from_modes(R)[0]
+
+
+def test_ground_state_bond_lengths():
+    """T* -> 0: aligned bonds solve (u_n - 1) - nu (u_{n-1} + u_{n+1}) = 0
+    (dH'/du_n = 0 for a straight chain), so interior bonds -> b (Eq. a3)."""
+    M = 16
+    N = M - 1
+    A = np.eye(N) - NU * (np.eye(N, k=1) + np.eye(N, k=-1))
+    u_ref = np.linalg.solve(A, np.ones(N))
+    pos = _relax(M, "euler", 0.1, 20000)
+    ell = np.sqrt((np.diff(pos, axis=1) ** 2).sum(axis=0))
+    assert np.allclose(ell, u_ref, rtol=1e-6)
+    assert u_ref[N // 2] == pytest.approx(B_FAC, rel=2e-3)
+
+
+def test_mode_step_is_first_order_consistent_with_ode():
+    """Deterministic (T* = 0) mode step converges to the bead ODE (b3): the
+    one-step error against a fine Euler integration falls like dtau^2."""
+    M = 12
+    pos0 = near_straight(M, 21, amp=0.1)
+    R0 = (dct_phi(M).T @ pos0.T).T[None]
+    errs = []
+    for dtau in [0.08, 0.04, 0.02]:
+        fine = oracle.step_euler(pos0[None], NU, 0.0, dtau / 400, 400)[0]
+        Rm = oracle.step_modes(R0, NU, 0.0, dtau, 1)
+        got = oracle.positions_from_modes(Rm)[0]
+        errs.append(np.abs(got - fine).max())
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 3.2 < r1 < 4.8 and 3.2 < r2 < 4.8, errs
+
+
+def test_euler_linear_stability_limit():
+    """Sec. 3a: Euler is unstable near dtau = 0.3; the linear bound is
+    2 / max zeta^l = 1 / (2 (1 + 2 nu)) ~ 0.294 for nu = 0.35.  Below it the
+    noise-free iteration relaxes to the ground state; just above it the
+    zig-zag mode no longer decays; well above it the chain blows up."""
+    M = 32
+    zl_max = oracle.tables(M, NU, TSTAR, 1.0)["zeta_l"].max()
+    assert 2 / zl_max == pytest.approx(1 / (2 * (1 + 2 * NU)), rel=0.01)
+    N = M - 1
+    A = np.eye(N) - NU * (np.eye(N, k=1) + np.eye(N, k=-1))
+    u_ref = np.linalg.solve(A, np.ones(N))
+    bonds = lambda x: np.sqrt((np.diff(x, axis=1) ** 2).sum(axis=0))
+    stable = _relax(M, "euler", 0.28, 4000)
+    assert np.allclose(bonds(stable), u_ref, rtol=1e-3)
+    marginal = _relax(M, "euler", 0.30, 4000)
+    assert np.abs(bonds(marginal) / u_ref - 1).max() > 0.5
+    with np.errstate(all="ignore"):
+        blown = _relax(M, "euler", 0.35, 2000)
+    assert not np.all(np.isfinite(blown))
+
+
+# ---------------------------------------------------------------- statistics
+def _two_bead_moments():
+    """Exact <l>, <l^2> for one bond: P(l) ~ l^2 exp(-(l-1)^2 / (2 T*))."""
+    w = lambda l, k: l ** (2 + k) * np.exp(-(l - 1) ** 2 / (2 * TSTAR))
+    z0 = scipy.integrate.quad(w, 0, 5, args=(0,), epsrel=1e-12)[0]
+    z1 = scipy.integrate.quad(w, 0, 5, args=(1,), epsrel=1e-12)[0]
+    z2 = scipy.integrate.quad(w, 0, 5, args=(2,), epsrel=1e-12)[0]
+    return z1 / z0, z2 / z0
+
+
+@pytest.mark.parametrize("scheme", ["euler", "modes"])
+def test_two_bead_equilibrium_by_quadrature(scheme):
+    """N = 1: no bending, so <l> and <l^2> follow from a 1-D quadrature."""
+    l1, l2 = _two_bead_moments()
+    assert l1 == pytest.approx(1.06576, abs=2e-5)
+    M, B, dtau = 2, 3000, 0.01
+    pos = np.stack([near_straight(M, s, amp=0.05) for s in range(B)])
+    samples = []
+    if scheme == "euler":
+        x = oracle.step_euler(pos, NU, TSTAR, dtau, 500, seed=1)
+        for k in range(10):
+            x = oracle.step_euler(x, NU, TSTAR, dtau, 100, seed=1, step0=500 + 100 * k)
+            samples.append(np.sqrt((np.diff(x, axis=2) ** 2).sum(axis=1)).ravel())
+    else:
+        R = np.einsum("np,ban->bap", dct_phi(M), pos)
+        R = oracle.step_modes(R, NU, TSTAR, dtau, 500, seed=1)
+        for k in range(10):
+            R = oracle.step_modes(R, NU, TSTAR, dtau, 100, seed=1, step0=500 + 100 * k)
+            x = oracle.positions_from_modes(R)
+            samples.append(np.sqrt((np.diff(x, axis=2) ** 2).sum(axis=1)).ravel())
+    ell = np.concatenate(samples)
+    se = ell.std() / np.sqrt(ell.size / 2)       # samples 1 tau apart: ~2 per tau
+    assert ell.mean() == pytest.approx(l1, abs=6 * se)
+    assert (ell ** 2).mean() == pytest.approx(l2, abs=6 * 2 * se)
+
+
+def _three_bead_moments():
+    """Exact <l>, <u1.u2>, <L^2> for N = 2 by Gauss-Legendre quadrature over
+    (l1, l2, cos theta) with weight l1^2 l2^2 exp(-H'/T*)."""
+    xl, wl = np.polynomial.legendre.leggauss(160)
+    lo, hi = 0.0, 3.0
+    l = 0.5 * (hi - lo) * xl + 0.5 * (hi + lo)
+    wlen = 0.5 * (hi - lo) * wl
+    xc, wc = np.polynomial.legendre.leggauss(160)
+    L1, L2, CT = np.meshgrid(l, l, xc, indexing="ij")
+    W = (wlen[:, None, None] * wlen[None, :, None] * wc[None, None, :])
+    H = 0.5 * (L1 - 1) ** 2 + 0.5 * (L2 - 1) ** 2 - NU * L1 * L2 * CT
+    H -= H.min()
+    P = W * L1 ** 2 * L2 ** 2 * np.exp(-H / TSTAR)
+    Z = P.sum()
+    mean_l = (P * 0.5 * (L1 + L2)).sum() / Z
+    dot = (P * L1 * L2 * CT).sum() / Z
+    e2e = (P * (L1 ** 2 + L2 ** 2 + 2 * L1 * L2 * CT)).sum() / Z
+    return mean_l, dot, e2e
+
+
+@pytest.mark.parametrize("scheme", ["euler", "modes"])
+def test_three_bead_equilibrium_by_quadrature(scheme):
+    """N = 2: <l>, <u1.u2>, <L^2> against 3-D quadrature (brute force)."""
+    ml, dot, e2e = _three_bead_moments()
+    M, B = 3, 2000
+    dtau = 0.01 if scheme == "euler" else 0.005
+    warm, every, ns = int(40 / dtau), int(2 / dtau), 12
+    pos = np.stack([near_straight(M, s, amp=0.05) for s in range(B)])
+    got_l, got_dot, got_e2e = [], [], []
+    if scheme == "euler":
+        x = oracle.step_euler(pos, NU, TSTAR, dtau, warm, seed=2)
+        step = warm
+        for _ in range(ns):
+            x = oracle.step_euler(x, NU, TSTAR, dtau, every, seed=2, step0=step)
+            step += every
+            u = np.diff(x, axis=2)
+            got_l.append(np.sqrt((u ** 2).sum(axis=1)).mean(axis=1))
+            got_dot.append((u[:, :, 0] * u[:, :, 1]).sum(axis=1))
+            got_e2e.append(((x[:, :, -1] - x[:, :, 0]) ** 2).sum(axis=1))
+    else:
+        R = np.einsum("np,ban->bap", dct_phi(M), pos)
+        R = oracle.step_modes(R, NU, TSTAR, dtau, warm, seed=2)
+        step = warm
+        for _ in range(ns):
+            R = oracle.step_modes(R, NU, TSTAR, dtau, every, seed=2, step0=step)
+            step += every
+            x = oracle.positions_from_modes(R)
+            u = np.diff(x, axis=2)
+            got_l.append(np.sqrt((u ** 2).sum(axis=1)).mean(axis=1))
+            got_dot.append((u[:, :, 0] * u[:, :, 1]).sum(axis=1))
+            got_e2e.append(((x[:, :, -1] - x[:, :, 0]) ** 2).sum(axis=1))
+    for got, ref in [(got_l, ml), (got_dot, dot), (got_e2e, e2e)]:
+        g = np.concatenate(got)
+        se = g.std() / np.sqrt(g.size / 2)
+        assert abs(g.mean() - ref) < max(6 * se, 2e-3 * abs(ref)), (scheme, g.mean(), ref, se)
+
+
+def test_generalised_equipartition_per_mode():
+    """Canonical equilibrium: <R_p . dH'/dR_p> = 3 T* for every mode p >= 1,
+    with dH'/dR_p = zeta_p R_p - Delta H_p (Eq. e10); paper tolerance 5%.
+    A soft chain (T* = 0.3) keeps the estimator's variance O(T*): for the
+    stiff dsDNA values it is a small difference of two large terms."""
+    M, B, dtau, T = 6, 400, 0.02, 0.3
+    pos = np.stack([near_straight(M, s, amp=0.05) for s in range(B)])
+    R = np.einsum("np,ban->bap", dct_phi(M), pos)
+    z = oracle.tables(M, NU, T, dtau)["zeta"]
+    warm, every = int(200 / dtau), int(5 / dtau)
+    R = oracle.step_modes(R, NU, T, dtau, warm, seed=4)
+    acc = np.zeros(M)
+    nsamp = 0
+    step = warm
+    for _ in range(40):
+        R = oracle.step_modes(R, NU, T, dtau, every, seed=4, step0=step)
+        step += every
+        for c in range(B):
+            dH = oracle.delta_h(R[c], NU)
+            acc += (R[c] * (z[None, :] * R[c] - dH)).sum(axis=0)
+        nsamp += B
+    ratio = acc[1:] / nsamp / (3 * T)
+    assert np.all(np.abs(ratio - 1) < 0.05), ratio
+
+
+def test_shear_stationary_covariance_of_free_modes():
+    """Eq. (btum) with the coupling off: each mode is a sheared OU process
+    whose stationary covariance solves a Lyapunov equation:
+    <R^x R^y> = gdot T* / (2 zeta^2), <R^y R^y> = T* / zeta."""
+    M, B, dtau, gdot = 4, 3000, 0.02, 0.1
+    z = oracle.tables(M, NU, TSTAR, dtau)["zeta"]
+    R = np.zeros((B, 3, M))
+    R = oracle.step_modes(R, NU, TSTAR, dtau, 3000, seed=6, gamma_dot=gdot,
+                          nonlinear=False)
+    xy, yy, step = [], [], 3000
+    for _ in range(10):
+        R = oracle.step_modes(R, NU, TSTAR, dtau, 300, seed=6, step0=step,
+                              gamma_dot=gdot, nonlinear=False)
+        step += 300
+        xy.append(R[:, 0, :] * R[:, 1, :])
+        yy.append(R[:, 1, :] ** 2)
+    xy, yy = np.concatenate(xy), np.concatenate(yy)
+    # samples are 6 tau apart, within a few relaxation times 1/zeta_1 ~ 8 tau
+    se = lambda a: 2.0 * a.std(axis=0) / np.sqrt(a.shape[0])
+    for p in (1, 2, 3):
+        assert abs(yy[:, p].mean() - TSTAR / z[p]) < 5 * se(yy)[p]
+        assert abs(xy[:, p].mean() - gdot * TSTAR / (2 * z[p] ** 2)) < 5 * se(xy)[p]
+    # the shear correlation is resolved (many standard errors from zero) at p = 1
+    assert xy[:, 1].mean() > 20 * se(xy)[1]
+
+
+def test_euler_shear_drift_from_ground_state():
+    """Eq. (btum): at the noise-free ground state the bead force vanishes,
+    so one Euler step moves bead n by gdot dtau y_n along x only."""
+    M, gdot, dtau = 10, 0.03, 0.1
+    N = M - 1
+    A = np.eye(N) - NU * (np.eye(N, k=1) + np.eye(N, k=-1))
+    u = np.linalg.solve(A, np.ones(N))
+    pos = np.zeros((3, M))
+    pos[1, 1:] = np.cumsum(u)
+    pos[1] -= 4.0
+    assert np.abs(oracle.bead_force(pos, NU)).max() < 1e-12
+    out = oracle.step_euler(pos[None], NU, 0.0, dtau, 1, gamma_dot=gdot)[0]
+    expect = pos.copy()
+    expect[0] += gdot * dtau * pos[1]
+    assert np.allclose(out, expect, atol=1e-13)
+
+
+def test_chain_observables_of_a_straight_chain():
+    """Observables of Sec. 5b on a straight chain, where all are closed form."""
+    M, s = 9, 2.5
+    e = np.array([0.6, 0.0, 0.8])
+    pos = e[:, None] * (np.arange(M) * s)[None, :] + np.array([1.0, -2.0, 3.0])[:, None]
+    o = oracle.chain_observables(pos[None])[0]
+    names = dict(zip(oracle.OBS_NAMES, o))
+    assert names["bond_mean"] == pytest.approx(s)
+    assert names["bond2_mean"] == pytest.approx(s * s)
+    assert names["L2"] == pytest.approx(((M - 1) * s) ** 2)
+    assert np.allclose(o[2:5], e * (M - 1) * s)
+    assert np.allclose(o[5:8], pos.mean(axis=1))
+    assert np.allclose(o[8:11], e * s)
+    mid = (M - 1) // 2
+    assert np.allclose(o[11:14], e * s * (mid - (M - 1) / 2))
+    assert names["xspan"] == pytest.approx(0.6 * (M - 1) * s)
