@@ -1,0 +1,195 @@
+/*
+ * dnamodes.h -- C ABI of the MI355X (gfx950) library for the mode-amplitude
+ * Langevin dynamics of semiflexible chains of Panja, Barkema & van Leeuwen,
+ * "Efficient simulation of semiflexible polymers" (arXiv:1411.3487).
+ *
+ * Model (Sec. 2, Eqs. a1-a3): a chain of M = N+1 beads r_0..r_N with bonds
+ * u_n = r_n - r_{n-1}, Hamiltonian
+ *     H = lambda/2 sum_n (|u_n| - d)^2 - kappa sum_n u_n . u_{n+1},
+ * reduced by nu = kappa/lambda and T* = kT/(lambda d^2); lengths in units of
+ * d, time in units of xi/lambda (Sec. 3, Eqs. b3-b5).  Overdamped Langevin
+ * dynamics with friction xi and thermal noise of variance 2 T*.
+ *
+ * Method (Secs. 3a-4c): positions are expanded in Rouse modes
+ * phi_{n,p} = sqrt(2/M) cos(p (n + 1/2) pi / M) (phi_{n,0} = 1/sqrt(M)),
+ * Eqs. (c1), (c8); each amplitude R_p obeys Eq. (e10),
+ *     dR_p/dtau = -zeta_p R_p + Delta H_p + G_p,
+ * and is advanced by the integrating factor of Eq. (d3) with the noise
+ * variance of Eq. (d6) and the coupling integral approximated by Eq. (f2):
+ *     R_p <- E_p R_p + C_p Delta H_p + W_p eta_p.
+ * The bead-space Euler scheme of Eqs. (b3)-(b5) is provided as the plain
+ * baseline.  Simple shear (Eq. btum) adds gamma_dot * y along x.
+ *
+ * Conventions for every function below:
+ *  - Return value: DM_OK (0) on success, a negative DM_E* code on failure;
+ *    dm_last_error() then gives a message.  A failed call leaves the
+ *    simulation state unchanged unless stated otherwise.
+ *  - Pointers marked "host" are read or written during the call only and
+ *    stay owned by the caller.  The context owns all device memory it
+ *    allocates (freed by dm_destroy).
+ *  - Work is enqueued on the HIP stream given to dm_init_chains and runs
+ *    asynchronously; calls that return host data synchronise that stream.
+ *  - A context is not thread-safe; separate contexts are independent.
+ *  - Array layout ("SoA"): one chain is 3*M doubles, component-major:
+ *    x_0..x_{M-1}, y_0.., z_0..; chains follow each other in chain order.
+ *  - Random numbers: Philox4x32-10 (Salmon et al., SC'11) with key
+ *    (seed lo, seed hi) and counter (index/4, chain, step lo,
+ *    (step hi << 8) | (component << 4) | tag); the four outputs give two
+ *    Box-Muller pairs, normal j of the block belongs to index 4*(index/4)+j.
+ *    tag 0 = mode step (index = mode p), 1 = Euler step (index = bead n).
+ *    Results are therefore independent of how chains are batched.
+ */
+#ifndef DNAMODES_H
+#define DNAMODES_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+#define DM_OK          0
+#define DM_EINVAL     -1   /* invalid argument */
+#define DM_ENOMEM     -2   /* device or host allocation failed */
+#define DM_EHIP       -3   /* a HIP runtime call failed */
+#define DM_ENONFINITE -4   /* the state became NaN or Inf */
+#define DM_ESTATE     -5   /* call out of order (e.g. stepping before set_params) */
+
+/* Arithmetic of the mode step. */
+#define DM_FP64    0  /* plain form: dense phi products on FP64 MFMA, separate
+                         force-stencil and mode-update kernels, FP64 state */
+#define DM_FP32    1  /* fused persistent kernel, FP32 MFMA transforms, FP32
+                         internal modes, FP64 centre of mass */
+#define DM_BF16X3  2  /* fused persistent kernel, transforms as three BF16 MFMA
+                         products (hi*hi + hi*lo + lo*hi) accumulated in FP32,
+                         FP32 internal modes, FP64 centre of mass */
+
+/* dm_observables() selection bits. */
+#define DM_OBS_CHAIN  1  /* per chain, current state, DM_NCHAIN_OBS doubles */
+#define DM_OBS_MODES  2  /* per chain, current |R_p|^2, p = 0..M_c-1 */
+#define DM_OBS_ACCUM  4  /* per length bucket, sums since the last reset */
+#define DM_OBS_RESET  8  /* zero the accumulators after copying them out */
+
+/* Per-chain observables (Sec. 5b): index into the DM_OBS_CHAIN block. */
+#define DM_NCHAIN_OBS   16
+#define DM_CO_BOND       0  /* mean bond length (1/N) sum_n |u_n| */
+#define DM_CO_L2         1  /* |L|^2, end-to-end vector L = r_N - r_0 */
+#define DM_CO_LX         2  /* L_x, L_y, L_z at 2, 3, 4 */
+#define DM_CO_CM         5  /* centre of mass r_cm = R_0 / sqrt(M), 5..7 */
+#define DM_CO_UMID       8  /* middle bond u_{M/2}, 8..10 */
+#define DM_CO_DMID      11  /* r_{(M-1)/2} - r_cm, 11..13 */
+#define DM_CO_XSPAN     14  /* max_n x_n - min_n x_n */
+#define DM_CO_BOND2     15  /* mean squared bond length (1/N) sum_n |u_n|^2 */
+
+/* Accumulator block of one length bucket: DM_NACC_HEAD doubles, then the
+   sum over samples and chains of |R_p|^2 for p = 0..M-1. */
+#define DM_NACC_HEAD     8
+#define DM_ACC_M         0  /* beads per chain in this bucket */
+#define DM_ACC_NCHAINS   1
+#define DM_ACC_NSAMPLES  2  /* number of sampling events */
+#define DM_ACC_BOND      3  /* sum of DM_CO_BOND over chains and samples */
+#define DM_ACC_BOND2     4  /* sum of DM_CO_BOND2 */
+#define DM_ACC_L2        5  /* sum of DM_CO_L2 */
+#define DM_ACC_MSDCM     6  /* sum of |r_cm - r_cm at the last reset|^2 */
+#define DM_ACC_DMID2     7  /* sum of |r_mid - r_cm|^2 */
+
+typedef struct dm_ctx dm_ctx;
+
+/* Model, time step and run parameters.
+   Physical units when lambda > 0 (pN/nm for lambda and kappa, pN nm for kT,
+   nm for a, pN ps/nm for xi, ps for dt, 1/ps for gamma_dot): then
+   nu = kappa/lambda, b = 1/(1-2nu), d = a/b, T* = kT/(lambda d^2) (Eqs. a2,
+   a3) and dtau = dt lambda/xi (Sec. 3).  Reduced units when lambda == 0:
+   T_star, nu, dt (= dtau) and gamma_dot are used as given. */
+typedef struct {
+    double lambda, kappa, kT, a, xi;
+    double T_star, nu;
+    double gamma_dot;        /* shear rate of Eq. (btum); 0 = no flow */
+    int32_t nonlinear;       /* 1: coupling Delta H_p of Eq. (e11) on;
+                                0: free Ornstein-Uhlenbeck modes (test mode) */
+    int32_t n_lengths;       /* entries in lengths[] / dt[] */
+    const int32_t *lengths;  /* host: chain lengths (beads) */
+    const double *dt;        /* host: time step for each length */
+    int32_t sample_every;    /* accumulate observables every this many
+                                mode steps (0 = never) */
+    int32_t check_finite;    /* 1: after each dm_step_* call check the state
+                                for NaN/Inf and return DM_ENONFINITE */
+} dm_params;
+
+/* Create a context for n_chains chains; beads[c] >= 2 is the number of beads
+   of chain c (host array, at most 2048).  pos0 (host, SoA, sum_c 3*beads[c] doubles, in
+   units of d) is the initial conformation; it is transformed to mode
+   amplitudes in FP64, Eq. (c1).  Chains are grouped into buckets of equal
+   length internally; chain c keeps Philox chain index c.  precision is one
+   of DM_FP64, DM_FP32, DM_BF16X3 (the fused paths need an even number of
+   beads, at most 512).  hip_stream is a hipStream_t (NULL = the null stream).
+   On success *out owns the context.  Errors: DM_EINVAL, DM_ENOMEM, DM_EHIP. */
+int dm_init_chains(dm_ctx **out, int32_t n_chains, const int32_t *beads,
+                   const double *pos0, uint64_t seed, int32_t precision,
+                   void *hip_stream);
+
+/* Set model parameters and time steps (Secs. 2, 3, 7b); builds the mode
+   tables of Eqs. (c8), (c9), (e9), (d3), (d6), (f2) in FP64 on the host for
+   every chain length and uploads them.  May be called again to change
+   parameters.  Errors: DM_EINVAL for nu outside [0, 1/2) (stability of
+   Eq. a2), T* <= 0, dt <= 0, or a chain length missing from lengths[]. */
+int dm_set_params(dm_ctx *ctx, const dm_params *p);
+
+/* Advance every chain by n_steps mode steps (Sec. 4, Eqs. e10, d3, d6, f2):
+   inverse transform of the internal modes to bond vectors, the nonlinear
+   bond force g_n = u_n (1/|u_n| - (1-2nu)) (Eqs. e4, e11), forward
+   transform to Delta H_p, and the per-mode update with Philox noise; the
+   centre-of-mass mode R_0 is a free random walk (FP64).  Asynchronous.
+   Errors: DM_ESTATE before dm_set_params, DM_ENONFINITE (check_finite). */
+int dm_step_modes(dm_ctx *ctx, int64_t n_steps);
+
+/* Advance every chain by n_steps bead-space Euler steps of reduced length
+   dtau (Eqs. b3-b5): r_n += dtau (h_{n+1} - h_n) + sqrt(2 T* dtau) eta_n with
+   h_n = (|u_n| - 1) u_n/|u_n| - nu (u_{n-1} + u_{n+1}), in FP64.  The
+   state is converted from and back to mode amplitudes once per call.
+   The scheme is unstable for dtau above about 0.3 (Sec. 3a).
+   Errors: DM_ESTATE, DM_EINVAL (dtau <= 0), DM_ENONFINITE (check_finite). */
+int dm_step_euler(dm_ctx *ctx, int64_t n_steps, double dtau);
+
+/* Observables of Sec. 5b.  which = OR of DM_OBS_* bits; the selected blocks
+   are written to out_host in the order CHAIN, MODES, ACCUM (see the layout
+   macros above).  out_len is the capacity in doubles; dm_observables_size()
+   gives the length needed.  Synchronises the stream.
+   Errors: DM_EINVAL if out_len is too small. */
+int dm_observables(dm_ctx *ctx, int32_t which, double *out_host,
+                   size_t out_len);
+int dm_observables_size(const dm_ctx *ctx, int32_t which, size_t *len);
+
+/* Bead positions (SoA, all chains, units of d) from the current mode
+   amplitudes, Eq. (c1), in FP64.  dst is a host pointer, or a device pointer
+   when dst_on_device != 0.  Synchronises the stream. */
+int dm_get_positions(dm_ctx *ctx, double *dst, int32_t dst_on_device);
+
+/* Mode amplitudes R_p (SoA, all chains, p = 0..M_c-1) in FP64.  Host dst. */
+int dm_get_modes(dm_ctx *ctx, double *dst_host);
+
+/* Serialise / restore the full state (mode amplitudes, step counters,
+   accumulators).  Philox is counter based, so a restored run continues
+   bit-identically.  dm_save_state with buf == NULL returns the size in *len. */
+int dm_save_state(dm_ctx *ctx, void *buf, size_t *len);
+int dm_load_state(dm_ctx *ctx, const void *buf, size_t len);
+
+/* Global step counter (mode and Euler steps share it: it is the Philox
+   step index). */
+int dm_get_step(const dm_ctx *ctx, int64_t *step);
+
+/* Synchronise the context's stream. */
+int dm_sync(dm_ctx *ctx);
+
+int dm_destroy(dm_ctx *ctx);
+
+/* Message of the last error on this context (ctx may be NULL for errors of
+   dm_init_chains).  Valid until the next call on the context. */
+const char *dm_last_error(const dm_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DNAMODES_H */

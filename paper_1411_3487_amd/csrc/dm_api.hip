@@ -1,0 +1,647 @@
+// dm_api.hip -- context, buckets and the C ABI of libdnamodes (dnamodes.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/dnamodes.h"
+#include "dm_fused.h"
+#include "dm_internal.h"
+#include "dm_tables.h"
+
+namespace {
+
+thread_local std::string g_init_error;
+
+struct Bucket {
+    int M = 0;
+    int n = 0;                       // chains
+    std::vector<int32_t> ids;        // caller chain index of each local chain
+    std::vector<int64_t> user_off;   // SoA offset (doubles) of each chain in caller order
+    double dtau = 0.0;
+    // device
+    int32_t *d_ids = nullptr;
+    int64_t *d_off = nullptr;
+    double *d_Ainv = nullptr;        // phi with column p = 0 zeroed (inverse, internal)
+    double *d_Apos = nullptr;        // phi (inverse, all modes)
+    double *d_Afwd = nullptr;        // phi^T (forward)
+    double *d_E = nullptr, *d_C = nullptr, *d_W = nullptr;
+    double *d_R64 = nullptr;         // n*3*M full mode amplitudes (FP64 state / scratch)
+    double *d_r = nullptr;           // n*3*M positions / workspace
+    double *d_F = nullptr;           // n*3*M forces
+    double *d_dH = nullptr;          // n*3*M coupling
+    double *d_obs = nullptr;         // n*16
+    double *d_m2 = nullptr;          // n*M
+    double *d_acc = nullptr;         // n*(8+M)
+    double *d_accsum = nullptr;      // 8+M
+    double *d_cm0 = nullptr;         // n*3
+    dm::FusedBucket fused;           // reduced-precision state and tables
+};
+
+}  // namespace
+
+struct dm_ctx {
+    int nchains = 0;
+    int precision = DM_FP64;
+    uint64_t seed = 0;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    std::vector<int32_t> beads;
+    std::vector<int64_t> offset;     // SoA offset of chain c (doubles)
+    size_t total = 0;                // sum of 3*beads
+    std::vector<Bucket> buckets;
+    bool have_params = false;
+    double T_star = 0, nu = 0, gamma_dot = 0;
+    int nonlinear = 1, sample_every = 0, check_finite = 0;
+    int64_t step = 0;
+    int *d_flag = nullptr;
+    std::string err;
+};
+
+namespace {
+
+int fail(dm_ctx *c, int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c)
+        c->err = buf;
+    else
+        g_init_error = buf;
+    return code;
+}
+
+#define DM_HIP(ctx, expr)                                                                    \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail((ctx), DM_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));      \
+    } while (0)
+
+template <typename T>
+int dalloc(dm_ctx *ctx, T **p, size_t count)
+{
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc((void **)p, sizeof(T) * count);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return fail(ctx, DM_ENOMEM, "hipMalloc of %zu bytes failed: %s", sizeof(T) * count,
+                    hipGetErrorString(e));
+    }
+    return DM_OK;
+}
+
+void free_bucket(Bucket &b)
+{
+    void *ptrs[] = {b.d_ids, b.d_off,  b.d_Ainv, b.d_Apos, b.d_Afwd, b.d_E,   b.d_C,
+                    b.d_W,   b.d_R64, b.d_r,    b.d_F,    b.d_dH,   b.d_obs, b.d_m2,
+                    b.d_acc, b.d_accsum, b.d_cm0};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    dm::fused_free(b.fused);
+}
+
+bool fused_precision(int p) { return p == DM_FP32 || p == DM_BF16X3; }
+
+// Positions of all chains of a bucket (FP64, bucket order) into b.d_r.
+int bucket_positions(dm_ctx *ctx, Bucket &b)
+{
+    if (fused_precision(ctx->precision))
+        DM_HIP(ctx, dm::fused_unpack_modes(b.fused, b.d_R64, b.M, b.n, ctx->stream));
+    DM_HIP(ctx, dm::launch_gemm_f64(b.d_Apos, b.d_R64, b.d_r, b.M, 3 * b.n, ctx->stream));
+    return DM_OK;
+}
+
+int observe(dm_ctx *ctx, int accumulate)
+{
+    for (Bucket &b : ctx->buckets) {
+        int rc = bucket_positions(ctx, b);
+        if (rc) return rc;
+        DM_HIP(ctx, dm::launch_chain_obs(b.d_r, b.d_R64, b.d_obs, b.d_m2, b.d_acc, b.d_cm0, b.M,
+                                         b.n, accumulate, ctx->stream));
+    }
+    return DM_OK;
+}
+
+int check_state(dm_ctx *ctx)
+{
+    DM_HIP(ctx, hipMemsetAsync(ctx->d_flag, 0, sizeof(int), ctx->stream));
+    for (Bucket &b : ctx->buckets) {
+        if (fused_precision(ctx->precision))
+            DM_HIP(ctx, dm::fused_check_finite(b.fused, b.M, b.n, ctx->d_flag, ctx->stream));
+        else
+            DM_HIP(ctx, dm::launch_check_finite_f64(b.d_R64, (size_t)3 * b.M * b.n, ctx->d_flag,
+                                                    ctx->stream));
+    }
+    int flag = 0;
+    DM_HIP(ctx, hipMemcpyAsync(&flag, ctx->d_flag, sizeof(int), hipMemcpyDeviceToHost,
+                               ctx->stream));
+    DM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (flag) return fail(ctx, DM_ENONFINITE, "state is not finite after step %lld",
+                          (long long)ctx->step);
+    return DM_OK;
+}
+
+// One FP64 plain-form mode step of one bucket at Philox step k.
+int plain_step(dm_ctx *ctx, Bucket &b, int64_t k)
+{
+    hipStream_t st = ctx->stream;
+    const int ncol = 3 * b.n;
+    if (ctx->nonlinear) {
+        DM_HIP(ctx, dm::launch_gemm_f64(b.d_Ainv, b.d_R64, b.d_r, b.M, ncol, st));
+        DM_HIP(ctx, dm::launch_stencil_f64(b.d_r, b.d_F, b.M, b.n, 1.0 - 2.0 * ctx->nu, st));
+        DM_HIP(ctx, dm::launch_gemm_f64(b.d_Afwd, b.d_F, b.d_dH, b.M, ncol, st));
+    }
+    DM_HIP(ctx, dm::launch_mode_update_f64(b.d_R64, b.d_dH, b.d_E, b.d_C, b.d_W, b.d_ids, b.M,
+                                           b.n, ctx->seed, nullptr, k,
+                                           ctx->gamma_dot * b.dtau, ctx->nonlinear, st));
+    return DM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dm_init_chains(dm_ctx **out, int32_t n_chains, const int32_t *beads, const double *pos0,
+                   uint64_t seed, int32_t precision, void *hip_stream)
+{
+    g_init_error.clear();
+    if (!out) return fail(nullptr, DM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n_chains <= 0) return fail(nullptr, DM_EINVAL, "n_chains must be positive");
+    if (!beads || !pos0) return fail(nullptr, DM_EINVAL, "beads and pos0 must be non-NULL");
+    if (precision != DM_FP64 && !fused_precision(precision))
+        return fail(nullptr, DM_EINVAL, "unknown precision %d", precision);
+    for (int c = 0; c < n_chains; ++c) {
+        const int M = beads[c];
+        if (M < 2) return fail(nullptr, DM_EINVAL, "chain %d has %d beads (need >= 2)", c, M);
+        if (M > 2048)
+            return fail(nullptr, DM_EINVAL, "chain %d has %d beads (at most 2048)", c, M);
+        if (fused_precision(precision) && !dm::fused_supports(M))
+            return fail(nullptr, DM_EINVAL,
+                        "chain %d: %d beads not supported by the fused path (even, 4..512)",
+                        c, M);
+    }
+    dm_ctx *ctx = new dm_ctx();
+    ctx->nchains = n_chains;
+    ctx->precision = precision;
+    ctx->seed = seed;
+    ctx->stream = (hipStream_t)hip_stream;
+    if (hipGetDevice(&ctx->device) != hipSuccess) {
+        delete ctx;
+        return fail(nullptr, DM_EHIP, "no HIP device");
+    }
+    ctx->beads.assign(beads, beads + n_chains);
+    ctx->offset.resize(n_chains);
+    int64_t off = 0;
+    std::map<int, int> bucket_of;
+    for (int c = 0; c < n_chains; ++c) {
+        ctx->offset[c] = off;
+        off += 3 * (int64_t)beads[c];
+        bucket_of[beads[c]] = 0;
+    }
+    ctx->total = (size_t)off;
+    int nb = 0;
+    for (auto &kv : bucket_of) kv.second = nb++;
+    ctx->buckets.resize(nb);
+    for (auto &kv : bucket_of) ctx->buckets[kv.second].M = kv.first;
+    for (int c = 0; c < n_chains; ++c) {
+        Bucket &b = ctx->buckets[bucket_of[beads[c]]];
+        b.ids.push_back(c);
+        b.user_off.push_back(ctx->offset[c]);
+        b.n++;
+    }
+    int rc = DM_OK;
+    auto bail = [&](int code) {
+        std::string msg = ctx->err;
+        for (Bucket &b : ctx->buckets) free_bucket(b);
+        if (ctx->d_flag) (void)hipFree(ctx->d_flag);
+        delete ctx;
+        g_init_error = msg;
+        return code;
+    };
+    if ((rc = dalloc(ctx, &ctx->d_flag, 1))) return bail(rc);
+    std::vector<double> phi, tmp;
+    for (Bucket &b : ctx->buckets) {
+        const size_t MM = (size_t)b.M * b.M, S = (size_t)3 * b.M * b.n;
+        if ((rc = dalloc(ctx, &b.d_ids, b.n)) || (rc = dalloc(ctx, &b.d_off, b.n)) ||
+            (rc = dalloc(ctx, &b.d_Ainv, MM)) || (rc = dalloc(ctx, &b.d_Apos, MM)) ||
+            (rc = dalloc(ctx, &b.d_Afwd, MM)) || (rc = dalloc(ctx, &b.d_E, b.M)) ||
+            (rc = dalloc(ctx, &b.d_C, b.M)) || (rc = dalloc(ctx, &b.d_W, b.M)) ||
+            (rc = dalloc(ctx, &b.d_R64, S)) || (rc = dalloc(ctx, &b.d_r, S)) ||
+            (rc = dalloc(ctx, &b.d_F, S)) || (rc = dalloc(ctx, &b.d_dH, S)) ||
+            (rc = dalloc(ctx, &b.d_obs, (size_t)16 * b.n)) ||
+            (rc = dalloc(ctx, &b.d_m2, (size_t)b.M * b.n)) ||
+            (rc = dalloc(ctx, &b.d_acc, (size_t)(8 + b.M) * b.n)) ||
+            (rc = dalloc(ctx, &b.d_accsum, (size_t)(8 + b.M))) ||
+            (rc = dalloc(ctx, &b.d_cm0, (size_t)3 * b.n)))
+            return bail(rc);
+        dm::rouse_matrix(b.M, phi);
+        std::vector<double> ainv(phi), afwd(MM);
+        for (int n = 0; n < b.M; ++n) {
+            ainv[(size_t)n * b.M] = 0.0;
+            for (int p = 0; p < b.M; ++p) afwd[(size_t)p * b.M + n] = phi[(size_t)n * b.M + p];
+        }
+        std::vector<double> pos(S), cm0((size_t)3 * b.n, 0.0);
+        for (int j = 0; j < b.n; ++j) {
+            const double *src = pos0 + b.user_off[j];
+            std::memcpy(&pos[(size_t)3 * b.M * j], src, sizeof(double) * 3 * b.M);
+            for (int a = 0; a < 3; ++a) {
+                double s = 0.0;
+                for (int n = 0; n < b.M; ++n) s += src[a * b.M + n];
+                cm0[3 * j + a] = s / b.M;
+            }
+        }
+        hipError_t e = hipSuccess;
+        auto up = [&](void *d, const void *h, size_t bytes) {
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, ctx->stream);
+        };
+        up(b.d_ids, b.ids.data(), sizeof(int32_t) * b.n);
+        up(b.d_off, b.user_off.data(), sizeof(int64_t) * b.n);
+        up(b.d_Ainv, ainv.data(), sizeof(double) * MM);
+        up(b.d_Apos, phi.data(), sizeof(double) * MM);
+        up(b.d_Afwd, afwd.data(), sizeof(double) * MM);
+        up(b.d_r, pos.data(), sizeof(double) * S);
+        up(b.d_cm0, cm0.data(), sizeof(double) * 3 * b.n);
+        if (e == hipSuccess)
+            e = hipMemsetAsync(b.d_acc, 0, sizeof(double) * (8 + b.M) * b.n, ctx->stream);
+        if (e == hipSuccess)
+            e = dm::launch_gemm_f64(b.d_Afwd, b.d_r, b.d_R64, b.M, 3 * b.n, ctx->stream);
+        if (e == hipSuccess && fused_precision(precision)) {
+            e = dm::fused_alloc(b.fused, b.M, b.n, precision == DM_BF16X3, phi);
+            if (e == hipSuccess) e = dm::fused_pack_modes(b.fused, b.d_R64, b.M, b.n, ctx->stream);
+        }
+        // the host staging buffers die with this scope: finish the uploads first
+        if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+        if (e != hipSuccess) {
+            fail(ctx, DM_EHIP, "init upload failed: %s", hipGetErrorString(e));
+            return bail(DM_EHIP);
+        }
+    }
+    *out = ctx;
+    return DM_OK;
+}
+
+int dm_set_params(dm_ctx *ctx, const dm_params *p)
+{
+    if (!ctx) return DM_EINVAL;
+    if (!p) return fail(ctx, DM_EINVAL, "params is NULL");
+    double T_star, nu, tunit = 1.0;
+    if (p->lambda > 0.0) {
+        if (!(p->kappa >= 0.0) || !(p->kT > 0.0) || !(p->a > 0.0) || !(p->xi > 0.0))
+            return fail(ctx, DM_EINVAL, "physical parameters must be positive");
+        nu = p->kappa / p->lambda;
+        const double b = 1.0 / (1.0 - 2.0 * nu), d = p->a / b;
+        T_star = p->kT / (p->lambda * d * d);
+        tunit = p->xi / p->lambda;  // ps per reduced time unit
+    } else {
+        T_star = p->T_star;
+        nu = p->nu;
+    }
+    if (!(nu >= 0.0 && nu < 0.5))
+        return fail(ctx, DM_EINVAL, "nu = %g outside [0, 1/2)", nu);
+    if (!(T_star > 0.0) || !std::isfinite(T_star))
+        return fail(ctx, DM_EINVAL, "T* = %g must be positive", T_star);
+    if (p->n_lengths <= 0 || !p->lengths || !p->dt)
+        return fail(ctx, DM_EINVAL, "lengths / dt tables are empty");
+    if (p->sample_every < 0) return fail(ctx, DM_EINVAL, "sample_every must be >= 0");
+    std::vector<double> dtau(ctx->buckets.size());
+    for (size_t i = 0; i < ctx->buckets.size(); ++i) {
+        int found = -1;
+        for (int j = 0; j < p->n_lengths; ++j)
+            if (p->lengths[j] == ctx->buckets[i].M) found = j;
+        if (found < 0)
+            return fail(ctx, DM_EINVAL, "no time step for chain length %d",
+                        ctx->buckets[i].M);
+        dtau[i] = p->dt[found] / tunit;
+        if (!(dtau[i] > 0.0) || !std::isfinite(dtau[i]))
+            return fail(ctx, DM_EINVAL, "time step for length %d must be positive",
+                        ctx->buckets[i].M);
+    }
+    const double gdot = p->gamma_dot * tunit;
+    if (!std::isfinite(gdot)) return fail(ctx, DM_EINVAL, "gamma_dot is not finite");
+    for (size_t i = 0; i < ctx->buckets.size(); ++i) {
+        Bucket &b = ctx->buckets[i];
+        dm::ModeCoefs mc;
+        dm::mode_coefficients(b.M, nu, T_star, dtau[i], mc);
+        DM_HIP(ctx, hipMemcpyAsync(b.d_E, mc.E.data(), sizeof(double) * b.M,
+                                   hipMemcpyHostToDevice, ctx->stream));
+        DM_HIP(ctx, hipMemcpyAsync(b.d_C, mc.C.data(), sizeof(double) * b.M,
+                                   hipMemcpyHostToDevice, ctx->stream));
+        DM_HIP(ctx, hipMemcpyAsync(b.d_W, mc.W.data(), sizeof(double) * b.M,
+                                   hipMemcpyHostToDevice, ctx->stream));
+        if (fused_precision(ctx->precision))
+            DM_HIP(ctx, dm::fused_set_coefs(b.fused, mc, b.M, 1.0 - 2.0 * nu, gdot * dtau[i],
+                                            ctx->stream));
+        DM_HIP(ctx, hipStreamSynchronize(ctx->stream));  // host tables go out of scope
+        b.dtau = dtau[i];
+    }
+    ctx->T_star = T_star;
+    ctx->nu = nu;
+    ctx->gamma_dot = gdot;
+    ctx->nonlinear = p->nonlinear ? 1 : 0;
+    ctx->sample_every = p->sample_every;
+    ctx->check_finite = p->check_finite ? 1 : 0;
+    ctx->have_params = true;
+    return DM_OK;
+}
+
+int dm_step_modes(dm_ctx *ctx, int64_t n_steps)
+{
+    if (!ctx) return DM_EINVAL;
+    if (!ctx->have_params) return fail(ctx, DM_ESTATE, "dm_set_params has not been called");
+    if (n_steps < 0) return fail(ctx, DM_EINVAL, "n_steps must be >= 0");
+    int64_t done = 0;
+    while (done < n_steps) {
+        // steps until the next sampling point (or the end of the request)
+        int64_t chunk = n_steps - done;
+        if (ctx->sample_every > 0) {
+            const int64_t to_sample = ctx->sample_every - (ctx->step % ctx->sample_every);
+            chunk = std::min(chunk, to_sample);
+        }
+        if (fused_precision(ctx->precision)) {
+            for (Bucket &b : ctx->buckets)
+                DM_HIP(ctx, dm::fused_step(b.fused, b.d_ids, b.M, b.n, ctx->seed, ctx->step,
+                                           (int)std::min<int64_t>(chunk, 1 << 30),
+                                           ctx->nonlinear, ctx->stream));
+        } else {
+            for (int64_t s = 0; s < chunk; ++s)
+                for (Bucket &b : ctx->buckets) {
+                    int rc = plain_step(ctx, b, ctx->step + s);
+                    if (rc) return rc;
+                }
+        }
+        ctx->step += chunk;
+        done += chunk;
+        if (ctx->sample_every > 0 && ctx->step % ctx->sample_every == 0) {
+            int rc = observe(ctx, 1);
+            if (rc) return rc;
+        }
+    }
+    if (ctx->check_finite) return check_state(ctx);
+    return DM_OK;
+}
+
+int dm_step_euler(dm_ctx *ctx, int64_t n_steps, double dtau)
+{
+    if (!ctx) return DM_EINVAL;
+    if (!ctx->have_params) return fail(ctx, DM_ESTATE, "dm_set_params has not been called");
+    if (!(dtau > 0.0) || !std::isfinite(dtau)) return fail(ctx, DM_EINVAL, "dtau must be > 0");
+    if (n_steps < 0 || n_steps > (1 << 30)) return fail(ctx, DM_EINVAL, "bad n_steps");
+    if (n_steps == 0) return DM_OK;
+    const double gdt = ctx->gamma_dot * dtau;
+    for (Bucket &b : ctx->buckets) {
+        int rc = bucket_positions(ctx, b);  // b.d_r = phi R (all modes, FP64)
+        if (rc) return rc;
+        DM_HIP(ctx, dm::launch_euler_f64(b.d_r, b.d_ids, b.M, b.n, ctx->nu, dtau, ctx->T_star,
+                                         gdt, ctx->seed, ctx->step, (int)n_steps, ctx->stream));
+        DM_HIP(ctx, dm::launch_gemm_f64(b.d_Afwd, b.d_r, b.d_R64, b.M, 3 * b.n, ctx->stream));
+        if (fused_precision(ctx->precision))
+            DM_HIP(ctx, dm::fused_pack_modes(b.fused, b.d_R64, b.M, b.n, ctx->stream));
+    }
+    ctx->step += n_steps;
+    if (ctx->check_finite) return check_state(ctx);
+    return DM_OK;
+}
+
+int dm_observables_size(const dm_ctx *ctx, int32_t which, size_t *len)
+{
+    if (!ctx || !len) return DM_EINVAL;
+    size_t n = 0;
+    if (which & DM_OBS_CHAIN) n += (size_t)DM_NCHAIN_OBS * ctx->nchains;
+    if (which & DM_OBS_MODES) n += ctx->total / 3;
+    if (which & DM_OBS_ACCUM)
+        for (const Bucket &b : ctx->buckets) n += DM_NACC_HEAD + b.M;
+    *len = n;
+    return DM_OK;
+}
+
+int dm_observables(dm_ctx *ctx, int32_t which, double *out_host, size_t out_len)
+{
+    if (!ctx) return DM_EINVAL;
+    size_t need = 0;
+    dm_observables_size(ctx, which, &need);
+    if (out_len < need || (need && !out_host))
+        return fail(ctx, DM_EINVAL, "output needs %zu doubles, got %zu", need, out_len);
+    double *o = out_host;
+    if (which & (DM_OBS_CHAIN | DM_OBS_MODES)) {
+        int rc = observe(ctx, 0);
+        if (rc) return rc;
+        DM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    }
+    if (which & DM_OBS_CHAIN) {
+        for (Bucket &b : ctx->buckets) {
+            std::vector<double> h((size_t)16 * b.n);
+            DM_HIP(ctx, hipMemcpy(h.data(), b.d_obs, sizeof(double) * h.size(),
+                                  hipMemcpyDeviceToHost));
+            for (int j = 0; j < b.n; ++j)
+                std::memcpy(o + (size_t)DM_NCHAIN_OBS * b.ids[j], &h[(size_t)16 * j],
+                            sizeof(double) * 16);
+        }
+        o += (size_t)DM_NCHAIN_OBS * ctx->nchains;
+    }
+    if (which & DM_OBS_MODES) {
+        for (Bucket &b : ctx->buckets) {
+            std::vector<double> h((size_t)b.M * b.n);
+            DM_HIP(ctx, hipMemcpy(h.data(), b.d_m2, sizeof(double) * h.size(),
+                                  hipMemcpyDeviceToHost));
+            for (int j = 0; j < b.n; ++j)
+                std::memcpy(o + ctx->offset[b.ids[j]] / 3, &h[(size_t)b.M * j],
+                            sizeof(double) * b.M);
+        }
+        o += ctx->total / 3;
+    }
+    if (which & DM_OBS_ACCUM) {
+        for (Bucket &b : ctx->buckets) {
+            const int w = 8 + b.M;
+            DM_HIP(ctx, dm::launch_reduce_chains(b.d_acc, b.d_accsum, w, b.n, ctx->stream));
+            DM_HIP(ctx, hipMemcpyAsync(o, b.d_accsum, sizeof(double) * w, hipMemcpyDeviceToHost,
+                                       ctx->stream));
+            DM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+            o[DM_ACC_M] = b.M;
+            o[DM_ACC_NCHAINS] = b.n;
+            o[DM_ACC_NSAMPLES] = b.n ? o[DM_ACC_NSAMPLES] / b.n : 0.0;
+            o += w;
+        }
+    }
+    if (which & DM_OBS_RESET) {
+        // the MSD reference becomes the current centre of mass
+        int rc = observe(ctx, 0);
+        if (rc) return rc;
+        for (Bucket &b : ctx->buckets) {
+            DM_HIP(ctx, hipMemsetAsync(b.d_acc, 0, sizeof(double) * (8 + b.M) * b.n,
+                                       ctx->stream));
+            DM_HIP(ctx, hipMemcpy2DAsync(b.d_cm0, 3 * sizeof(double), b.d_obs + DM_CO_CM,
+                                         16 * sizeof(double), 3 * sizeof(double), b.n,
+                                         hipMemcpyDeviceToDevice, ctx->stream));
+        }
+        DM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    }
+    return DM_OK;
+}
+
+int dm_get_positions(dm_ctx *ctx, double *dst, int32_t dst_on_device)
+{
+    if (!ctx || !dst) return ctx ? fail(ctx, DM_EINVAL, "dst is NULL") : DM_EINVAL;
+    for (Bucket &b : ctx->buckets) {
+        int rc = bucket_positions(ctx, b);
+        if (rc) return rc;
+        if (dst_on_device) {
+            DM_HIP(ctx, dm::launch_scatter_chains(b.d_r, dst, b.d_off, 3 * b.M, b.n,
+                                                  ctx->stream));
+        } else {
+            std::vector<double> h((size_t)3 * b.M * b.n);
+            DM_HIP(ctx, hipMemcpyAsync(h.data(), b.d_r, sizeof(double) * h.size(),
+                                       hipMemcpyDeviceToHost, ctx->stream));
+            DM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+            for (int j = 0; j < b.n; ++j)
+                std::memcpy(dst + b.user_off[j], &h[(size_t)3 * b.M * j],
+                            sizeof(double) * 3 * b.M);
+        }
+    }
+    DM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return DM_OK;
+}
+
+int dm_get_modes(dm_ctx *ctx, double *dst)
+{
+    if (!ctx || !dst) return ctx ? fail(ctx, DM_EINVAL, "dst is NULL") : DM_EINVAL;
+    for (Bucket &b : ctx->buckets) {
+        if (fused_precision(ctx->precision))
+            DM_HIP(ctx, dm::fused_unpack_modes(b.fused, b.d_R64, b.M, b.n, ctx->stream));
+        std::vector<double> h((size_t)3 * b.M * b.n);
+        DM_HIP(ctx, hipMemcpyAsync(h.data(), b.d_R64, sizeof(double) * h.size(),
+                                   hipMemcpyDeviceToHost, ctx->stream));
+        DM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        for (int j = 0; j < b.n; ++j)
+            std::memcpy(dst + b.user_off[j], &h[(size_t)3 * b.M * j], sizeof(double) * 3 * b.M);
+    }
+    return DM_OK;
+}
+
+// State blob: header, then per bucket the FP64 modes (n*3*M), the centre of
+// mass reference (n*3) and the per-chain accumulators (n*(8+M)).
+struct StateHeader {
+    uint64_t magic;
+    int64_t step;
+    int32_t nchains, precision, nbuckets, pad;
+};
+static const uint64_t kStateMagic = 0x314d4f444d4e4144ull;  // "DANMDOM1"
+
+static size_t state_size(const dm_ctx *ctx)
+{
+    size_t s = sizeof(StateHeader);
+    for (const Bucket &b : ctx->buckets)
+        s += sizeof(int32_t) * 2 + sizeof(double) * ((size_t)3 * b.M * b.n + 3 * (size_t)b.n +
+                                                     (size_t)(8 + b.M) * b.n);
+    return s;
+}
+
+int dm_save_state(dm_ctx *ctx, void *buf, size_t *len)
+{
+    if (!ctx || !len) return DM_EINVAL;
+    const size_t need = state_size(ctx);
+    if (!buf) {
+        *len = need;
+        return DM_OK;
+    }
+    if (*len < need) return fail(ctx, DM_EINVAL, "state buffer needs %zu bytes", need);
+    char *p = (char *)buf;
+    StateHeader h{kStateMagic, ctx->step, ctx->nchains, ctx->precision,
+                  (int32_t)ctx->buckets.size(), 0};
+    std::memcpy(p, &h, sizeof h);
+    p += sizeof h;
+    for (Bucket &b : ctx->buckets) {
+        int32_t mn[2] = {b.M, b.n};
+        std::memcpy(p, mn, sizeof mn);
+        p += sizeof mn;
+        if (fused_precision(ctx->precision))
+            DM_HIP(ctx, dm::fused_unpack_modes(b.fused, b.d_R64, b.M, b.n, ctx->stream));
+        const size_t s1 = sizeof(double) * 3 * b.M * b.n, s2 = sizeof(double) * 3 * b.n,
+                     s3 = sizeof(double) * (8 + b.M) * b.n;
+        DM_HIP(ctx, hipMemcpyAsync(p, b.d_R64, s1, hipMemcpyDeviceToHost, ctx->stream));
+        DM_HIP(ctx, hipMemcpyAsync(p + s1, b.d_cm0, s2, hipMemcpyDeviceToHost, ctx->stream));
+        DM_HIP(ctx, hipMemcpyAsync(p + s1 + s2, b.d_acc, s3, hipMemcpyDeviceToHost, ctx->stream));
+        p += s1 + s2 + s3;
+    }
+    DM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    *len = need;
+    return DM_OK;
+}
+
+int dm_load_state(dm_ctx *ctx, const void *buf, size_t len)
+{
+    if (!ctx || !buf) return DM_EINVAL;
+    if (len < state_size(ctx)) return fail(ctx, DM_EINVAL, "state blob too short");
+    const char *p = (const char *)buf;
+    StateHeader h;
+    std::memcpy(&h, p, sizeof h);
+    p += sizeof h;
+    if (h.magic != kStateMagic || h.nchains != ctx->nchains || h.precision != ctx->precision ||
+        h.nbuckets != (int32_t)ctx->buckets.size())
+        return fail(ctx, DM_EINVAL, "state blob does not match this context");
+    const char *q = p;
+    for (Bucket &b : ctx->buckets) {  // validate before touching the state
+        int32_t mn[2];
+        std::memcpy(mn, q, sizeof mn);
+        if (mn[0] != b.M || mn[1] != b.n)
+            return fail(ctx, DM_EINVAL, "state blob bucket mismatch");
+        q += sizeof mn + sizeof(double) * ((size_t)3 * b.M * b.n + 3 * (size_t)b.n +
+                                           (size_t)(8 + b.M) * b.n);
+    }
+    for (Bucket &b : ctx->buckets) {
+        p += 2 * sizeof(int32_t);
+        const size_t s1 = sizeof(double) * 3 * b.M * b.n, s2 = sizeof(double) * 3 * b.n,
+                     s3 = sizeof(double) * (8 + b.M) * b.n;
+        DM_HIP(ctx, hipMemcpyAsync(b.d_R64, p, s1, hipMemcpyHostToDevice, ctx->stream));
+        DM_HIP(ctx, hipMemcpyAsync(b.d_cm0, p + s1, s2, hipMemcpyHostToDevice, ctx->stream));
+        DM_HIP(ctx, hipMemcpyAsync(b.d_acc, p + s1 + s2, s3, hipMemcpyHostToDevice, ctx->stream));
+        if (fused_precision(ctx->precision))
+            DM_HIP(ctx, dm::fused_pack_modes(b.fused, b.d_R64, b.M, b.n, ctx->stream));
+        p += s1 + s2 + s3;
+    }
+    DM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    ctx->step = h.step;
+    return DM_OK;
+}
+
+int dm_get_step(const dm_ctx *ctx, int64_t *step)
+{
+    if (!ctx || !step) return DM_EINVAL;
+    *step = ctx->step;
+    return DM_OK;
+}
+
+int dm_sync(dm_ctx *ctx)
+{
+    if (!ctx) return DM_EINVAL;
+    DM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return DM_OK;
+}
+
+int dm_destroy(dm_ctx *ctx)
+{
+    if (!ctx) return DM_EINVAL;
+    (void)hipStreamSynchronize(ctx->stream);
+    for (Bucket &b : ctx->buckets) free_bucket(b);
+    if (ctx->d_flag) (void)hipFree(ctx->d_flag);
+    delete ctx;
+    return DM_OK;
+}
+
+const char *dm_last_error(const dm_ctx *ctx)
+{
+    return ctx ? ctx->err.c_str() : g_init_error.c_str();
+}
+
+}  // extern "C"

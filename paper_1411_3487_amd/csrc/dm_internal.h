@@ -1,0 +1,58 @@
+// dm_internal.h -- launchers shared by the library's translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dm {
+
+// Plain-form (FP64) kernels, dm_plain.hip.  Every launcher only enqueues on
+// `st` and returns the launch status.
+
+// Y[c][i] = sum_k A[i*M + k] X[c*M + k] for c < ncol, i, k < M (FP64 MFMA).
+hipError_t launch_gemm_f64(const double *A, const double *X, double *Y, int M,
+                           int ncol, hipStream_t st);
+
+// Bead forces of the nonlinear bond term from internal positions r:
+// g_n = u_n (1/|u_n| - lin), F_n = g_n - g_{n+1} (Eqs. e4, e11).
+hipError_t launch_stencil_f64(const double *r, double *F, int M, int nch,
+                              double lin, hipStream_t st);
+
+// R_p <- E_p R_p + C_p dH_p + W_p eta_p, then R^x_p += gdt E_p R^y_p(old);
+// p = 0 takes no coupling.  Philox step index = (*step_dev) + step_off
+// (step_dev may be null).
+hipError_t launch_mode_update_f64(double *R, const double *dH, const double *E,
+                                  const double *C, const double *W,
+                                  const int32_t *ids, int M, int nch,
+                                  uint64_t seed, const int64_t *step_dev,
+                                  int64_t step_off, double gdt, int nonlinear,
+                                  hipStream_t st);
+
+// n_steps bead-space Euler steps on positions pos (SoA), one block per chain.
+hipError_t launch_euler_f64(double *pos, const int32_t *ids, int M, int nch,
+                            double nu, double dtau, double T_star, double gdt,
+                            uint64_t seed, int64_t step0, int n_steps,
+                            hipStream_t st);
+
+// Per-chain observables from positions and modes; writes obs[c*16 + .] and
+// m2[c*M + p] = |R_p|^2, and adds into the per-chain accumulators
+// acc[c*(8+M) + .] when accumulate != 0.
+hipError_t launch_chain_obs(const double *pos, const double *R, double *obs,
+                            double *m2, double *acc, const double *cm0, int M,
+                            int nch, int accumulate, hipStream_t st);
+
+// out[j] = sum_c acc[c*width + j], summed over chains in order.
+hipError_t launch_reduce_chains(const double *acc, double *out, int width,
+                                int nch, hipStream_t st);
+
+// *flag |= 1 if any of x[0..n) is NaN or Inf (flag is not cleared).
+hipError_t launch_check_finite_f64(const double *x, size_t n, int *flag,
+                                   hipStream_t st);
+hipError_t launch_check_finite_f32(const float *x, size_t n, int *flag,
+                                   hipStream_t st);
+
+// dst[off[c] + i] = src[c*len + i] for i < len (bucket -> caller order).
+hipError_t launch_scatter_chains(const double *src, double *dst,
+                                 const int64_t *off, int len, int nch,
+                                 hipStream_t st);
+
+}  // namespace dm

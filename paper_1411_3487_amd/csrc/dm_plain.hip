@@ -1,0 +1,458 @@
+// dm_plain.hip -- the plain FP64 form of the mode step and the bead-space
+// Euler baseline, as separate kernels (gfx950).
+//
+// Data layout in HBM: a bucket of nch chains of M beads stores positions,
+// forces and mode amplitudes as nch*3 columns of M doubles (SoA, column
+// (chain, component) contiguous in the bead or mode index).  A transform is
+// then one GEMM Y = A X^T with a square M x M table A and 3*nch columns:
+//   inverse  r_n  = sum_{p>=1} phi_{n,p} R_p     (Eq. c1, internal coords)
+//   forward  dH_p = sum_n phi_{n,p} F_n          (Eqs. c5, e11)
+#include "dm_internal.h"
+#include "dm_rng.h"
+
+namespace dm {
+namespace {
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// --------------------------------------------------------------------------
+// GEMM on FP64 MFMA (v_mfma_f64_16x16x4f64).  Workgroup tile 64 rows x 64
+// columns, 4 waves of 32 x 32 (2 x 2 MFMA tiles), K staged through LDS in
+// chunks of 16.  MFMA operand layout per lane l: A[i = l%16][k = l/16],
+// B[k = l/16][j = l%16]; result D[i = l/16 + 4r][j = l%16], r = 0..3 (the
+// FP64 instruction interleaves its four result rows across the lane groups).
+// --------------------------------------------------------------------------
+constexpr int kGemmBM = 64, kGemmBN = 64, kGemmBK = 16;
+
+__global__ __launch_bounds__(256) void gemm_f64_kernel(const double *__restrict__ A,
+                                                       const double *__restrict__ X,
+                                                       double *__restrict__ Y, int M,
+                                                       int ncol)
+{
+    __shared__ double As[kGemmBM][kGemmBK + 1];
+    __shared__ double Xs[kGemmBN][kGemmBK + 1];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wi = wave >> 1, wj = wave & 1;
+    const int i0 = blockIdx.x * kGemmBM;
+    const int c0 = blockIdx.y * kGemmBN;
+    f64x4 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+
+    for (int k0 = 0; k0 < M; k0 += kGemmBK) {
+#pragma unroll
+        for (int e = 0; e < (kGemmBM * kGemmBK) / 256; ++e) {
+            const int idx = tid + 256 * e;
+            const int row = idx / kGemmBK, kk = idx % kGemmBK;
+            const int gk = k0 + kk;
+            const int gi = i0 + row, gc = c0 + row;
+            As[row][kk] = (gi < M && gk < M) ? A[(size_t)gi * M + gk] : 0.0;
+            Xs[row][kk] = (gc < ncol && gk < M) ? X[(size_t)gc * M + gk] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < kGemmBK; ks += 4) {
+            double a[2], b[2];
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                a[t] = As[32 * wi + 16 * t + (lane & 15)][ks + (lane >> 4)];
+                b[t] = Xs[32 * wj + 16 * t + (lane & 15)][ks + (lane >> 4)];
+            }
+#pragma unroll
+            for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+                for (int tj = 0; tj < 2; ++tj)
+                    acc[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ti], b[tj],
+                                                                      acc[ti][tj], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < 2; ++tj) {
+            const int c = c0 + 32 * wj + 16 * tj + (lane & 15);
+            const int ib = i0 + 32 * wi + 16 * ti + (lane >> 4);
+            if (c >= ncol) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                if (ib + 4 * r < M) Y[(size_t)c * M + ib + 4 * r] = acc[ti][tj][r];
+        }
+}
+
+// --------------------------------------------------------------------------
+// Force stencil, one thread per (chain, bead).  Bonds u_n = r_n - r_{n-1}
+// (n = 1..M-1), g_n = u_n (1/|u_n| - lin) with lin = 1 - 2 nu (Eq. e4),
+// F_n = g_n - g_{n+1} with g_0 = g_M = 0.
+// --------------------------------------------------------------------------
+__device__ __forceinline__ void bond_g(const double *__restrict__ x, int M, int m,
+                                       double lin, double g[3])
+{
+    const double ux = x[m] - x[m - 1];
+    const double uy = x[M + m] - x[M + m - 1];
+    const double uz = x[2 * M + m] - x[2 * M + m - 1];
+    const double l = sqrt(ux * ux + uy * uy + uz * uz);
+    const double f = 1.0 / l - lin;
+    g[0] = ux * f;
+    g[1] = uy * f;
+    g[2] = uz * f;
+}
+
+__global__ __launch_bounds__(256) void stencil_f64_kernel(const double *__restrict__ r,
+                                                          double *__restrict__ F, int M,
+                                                          int nch, double lin)
+{
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (size_t)nch * M) return;
+    const int c = (int)(idx / M), n = (int)(idx % M);
+    const double *x = r + (size_t)c * 3 * M;
+    double g0[3] = {0.0, 0.0, 0.0}, g1[3] = {0.0, 0.0, 0.0};
+    if (n >= 1) bond_g(x, M, n, lin, g0);
+    if (n + 1 <= M - 1) bond_g(x, M, n + 1, lin, g1);
+    double *f = F + (size_t)c * 3 * M;
+    f[n] = g0[0] - g1[0];
+    f[M + n] = g0[1] - g1[1];
+    f[2 * M + n] = g0[2] - g1[2];
+}
+
+// --------------------------------------------------------------------------
+// Mode update (Eqs. d3, d6, f2, btum), one thread per (chain, 4 modes).
+// --------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void mode_update_f64_kernel(
+    double *__restrict__ R, const double *__restrict__ dH, const double *__restrict__ E,
+    const double *__restrict__ C, const double *__restrict__ W,
+    const int32_t *__restrict__ ids, int M, int nch, uint64_t seed,
+    const int64_t *__restrict__ step_dev, int64_t step_off, double gdt, int nonlinear)
+{
+    const int nq = (M + 3) / 4;
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (size_t)nch * nq) return;
+    const int c = (int)(idx / nq), q = (int)(idx % nq);
+    const int64_t k = (step_dev ? *step_dev : 0) + step_off;
+    const uint32_t chain = (uint32_t)ids[c];
+    double z[3][4];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+        normals4_f64(noise_bits(seed, (uint32_t)q, chain, k, (uint32_t)a, kTagMode), z[a]);
+    double *Rc = R + (size_t)c * 3 * M;
+    const double *dHc = dH + (size_t)c * 3 * M;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int p = 4 * q + j;
+        if (p >= M) break;
+        const double ry = Rc[M + p];
+        const double e = E[p], w = W[p], cc = C[p];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            double v = e * Rc[a * M + p] + w * z[a][j];
+            if (nonlinear && p > 0) v += cc * dHc[a * M + p];
+            Rc[a * M + p] = v;
+        }
+        Rc[p] += gdt * e * ry;
+    }
+}
+
+// --------------------------------------------------------------------------
+// Bead-space Euler (Eqs. b3-b5, btum).  One block per chain, positions held
+// in LDS across all steps; thread t owns beads 4t..4t+3.
+//   u_m = x_m - x_{m-1} for 1 <= m <= M-1, else 0;
+//   h_m = (|u_m| - 1) u_m/|u_m| - nu (u_{m-1} + u_{m+1}) for 1 <= m <= M-1;
+//   x_n += dtau (h_{n+1} - h_n) + sqrt(2 T* dtau) eta_n;  x_n += gdt y_n(old).
+// --------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void euler_f64_kernel(double *__restrict__ pos,
+                                                         const int32_t *__restrict__ ids,
+                                                         int M, double nu, double dtau,
+                                                         double amp, double gdt,
+                                                         uint64_t seed, int64_t step0,
+                                                         int n_steps)
+{
+    extern __shared__ double xs[];  // 3*M
+    const int c = blockIdx.x, tid = threadIdx.x;
+    double *P = pos + (size_t)c * 3 * M;
+    for (int i = tid; i < 3 * M; i += blockDim.x) xs[i] = P[i];
+    __syncthreads();
+    const int nq = (M + 3) / 4;
+    const bool active = tid < nq;
+    const int n0 = 4 * tid;
+    const uint32_t chain = (uint32_t)ids[c];
+    for (int s = 0; s < n_steps; ++s) {
+        double nx[3][4];
+        if (active) {
+            const int64_t k = step0 + s;
+            double z[3][4];
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+                normals4_f64(noise_bits(seed, (uint32_t)tid, chain, k, (uint32_t)a, kTagEuler),
+                             z[a]);
+            // bonds m = n0-1 .. n0+5  -> u[0..6]
+            double u[3][7];
+#pragma unroll
+            for (int j = 0; j < 7; ++j) {
+                const int m = n0 - 1 + j;
+                const bool ok = (m >= 1) && (m <= M - 1);
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+                    u[a][j] = ok ? xs[a * M + m] - xs[a * M + m - 1] : 0.0;
+            }
+            // h_m for m = n0 .. n0+4 -> h[0..4] (u index j = m - n0 + 1)
+            double h[3][5];
+#pragma unroll
+            for (int j = 0; j < 5; ++j) {
+                const int m = n0 + j;
+                const bool ok = (m >= 1) && (m <= M - 1);
+                const double l = sqrt(u[0][j + 1] * u[0][j + 1] + u[1][j + 1] * u[1][j + 1] +
+                                      u[2][j + 1] * u[2][j + 1]);
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+                    h[a][j] = ok ? (l - 1.0) * u[a][j + 1] / l - nu * (u[a][j] + u[a][j + 2])
+                                 : 0.0;
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int n = n0 + j;
+                if (n >= M) break;
+                const double y_old = xs[M + n];
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+                    nx[a][j] = xs[a * M + n] + (dtau * (h[a][j + 1] - h[a][j]) + amp * z[a][j]);
+                nx[0][j] += gdt * y_old;
+            }
+        }
+        __syncthreads();
+        if (active) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int n = n0 + j;
+                if (n >= M) break;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) xs[a * M + n] = nx[a][j];
+            }
+        }
+        __syncthreads();
+    }
+    for (int i = tid; i < 3 * M; i += blockDim.x) P[i] = xs[i];
+}
+
+// --------------------------------------------------------------------------
+// Observables (Sec. 5b): one wave per chain, FP64 wavefront reductions.
+// --------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_min(double v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+__global__ __launch_bounds__(64) void chain_obs_kernel(const double *__restrict__ pos,
+                                                       const double *__restrict__ R,
+                                                       double *__restrict__ obs,
+                                                       double *__restrict__ m2,
+                                                       double *__restrict__ acc,
+                                                       const double *__restrict__ cm0,
+                                                       int M, int accumulate)
+{
+    const int c = blockIdx.x, lane = threadIdx.x;
+    const double *x = pos + (size_t)c * 3 * M;
+    double ls = 0.0, l2s = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
+    double xmin = x[0], xmax = x[0];
+    for (int n = lane; n < M; n += 64) {
+        sx += x[n];
+        sy += x[M + n];
+        sz += x[2 * M + n];
+        xmin = fmin(xmin, x[n]);
+        xmax = fmax(xmax, x[n]);
+        if (n >= 1) {
+            const double ux = x[n] - x[n - 1], uy = x[M + n] - x[M + n - 1],
+                         uz = x[2 * M + n] - x[2 * M + n - 1];
+            const double q = ux * ux + uy * uy + uz * uz;
+            ls += sqrt(q);
+            l2s += q;
+        }
+    }
+    ls = wave_sum(ls);
+    l2s = wave_sum(l2s);
+    sx = wave_sum(sx);
+    sy = wave_sum(sy);
+    sz = wave_sum(sz);
+    xmin = wave_min(xmin);
+    xmax = wave_max(xmax);
+    const double *Rc = R + (size_t)c * 3 * M;
+    double *accc = acc + (size_t)c * (8 + M);
+    for (int p = lane; p < M; p += 64) {
+        const double v = Rc[p] * Rc[p] + Rc[M + p] * Rc[M + p] + Rc[2 * M + p] * Rc[2 * M + p];
+        m2[(size_t)c * M + p] = v;
+        if (accumulate) accc[8 + p] += v;
+    }
+    if (lane == 0) {
+        double o[16];
+        o[0] = ls / (M - 1);
+        const double Lx = x[M - 1] - x[0], Ly = x[2 * M - 1] - x[M],
+                     Lz = x[3 * M - 1] - x[2 * M];
+        o[1] = Lx * Lx + Ly * Ly + Lz * Lz;
+        o[2] = Lx;
+        o[3] = Ly;
+        o[4] = Lz;
+        o[5] = sx / M;
+        o[6] = sy / M;
+        o[7] = sz / M;
+        const int m = M / 2, mid = (M - 1) / 2;
+        for (int a = 0; a < 3; ++a) {
+            o[8 + a] = x[a * M + m] - x[a * M + m - 1];
+            o[11 + a] = x[a * M + mid] - o[5 + a];
+        }
+        o[14] = xmax - xmin;
+        o[15] = l2s / (M - 1);
+        for (int j = 0; j < 16; ++j) obs[(size_t)c * 16 + j] = o[j];
+        if (accumulate) {
+            const double dx = o[5] - cm0[3 * c], dy = o[6] - cm0[3 * c + 1],
+                         dz = o[7] - cm0[3 * c + 2];
+            accc[2] += 1.0;
+            accc[3] += o[0];
+            accc[4] += o[15];
+            accc[5] += o[1];
+            accc[6] += dx * dx + dy * dy + dz * dz;
+            accc[7] += o[11] * o[11] + o[12] * o[12] + o[13] * o[13];
+        }
+    }
+}
+
+__global__ void reduce_chains_kernel(const double *__restrict__ acc, double *__restrict__ out,
+                                     int width, int nch)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= width) return;
+    double s = 0.0;
+    for (int c = 0; c < nch; ++c) s += acc[(size_t)c * width + j];
+    out[j] = s;
+}
+
+template <typename T>
+__global__ void check_finite_kernel(const T *__restrict__ x, size_t n, int *flag)
+{
+    int bad = 0;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        bad |= !isfinite(x[i]);
+    if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
+}
+
+__global__ void scatter_chains_kernel(const double *__restrict__ src, double *__restrict__ dst,
+                                      const int64_t *__restrict__ off, int len, int nch)
+{
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (size_t)nch * len) return;
+    const int c = (int)(idx / len), i = (int)(idx % len);
+    dst[off[c] + i] = src[idx];
+}
+
+inline unsigned blocks_for(size_t n, unsigned t) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace
+
+hipError_t launch_gemm_f64(const double *A, const double *X, double *Y, int M, int ncol,
+                           hipStream_t st)
+{
+    if (M <= 0 || ncol <= 0) return hipSuccess;
+    dim3 grid((M + kGemmBM - 1) / kGemmBM, (ncol + kGemmBN - 1) / kGemmBN);
+    hipLaunchKernelGGL(gemm_f64_kernel, grid, dim3(256), 0, st, A, X, Y, M, ncol);
+    return hipGetLastError();
+}
+
+hipError_t launch_stencil_f64(const double *r, double *F, int M, int nch, double lin,
+                              hipStream_t st)
+{
+    const size_t n = (size_t)nch * M;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(stencil_f64_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, r, F, M,
+                       nch, lin);
+    return hipGetLastError();
+}
+
+hipError_t launch_mode_update_f64(double *R, const double *dH, const double *E, const double *C,
+                                  const double *W, const int32_t *ids, int M, int nch,
+                                  uint64_t seed, const int64_t *step_dev, int64_t step_off,
+                                  double gdt, int nonlinear, hipStream_t st)
+{
+    const size_t n = (size_t)nch * ((M + 3) / 4);
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(mode_update_f64_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, R,
+                       dH, E, C, W, ids, M, nch, seed, step_dev, step_off, gdt, nonlinear);
+    return hipGetLastError();
+}
+
+hipError_t launch_euler_f64(double *pos, const int32_t *ids, int M, int nch, double nu,
+                            double dtau, double T_star, double gdt, uint64_t seed, int64_t step0,
+                            int n_steps, hipStream_t st)
+{
+    if (nch == 0 || n_steps == 0) return hipSuccess;
+    const int nq = (M + 3) / 4;
+    if (nq > 1024) return hipErrorInvalidValue;
+    const int threads = ((nq + 63) / 64) * 64;
+    const size_t lds = sizeof(double) * 3 * (size_t)M;
+    if (lds > 64 * 1024) return hipErrorInvalidValue;  // positions must fit the LDS
+    hipLaunchKernelGGL(euler_f64_kernel, dim3(nch), dim3(threads), lds, st, pos, ids, M, nu,
+                       dtau, sqrt(2.0 * T_star * dtau), gdt, seed, step0, n_steps);
+    return hipGetLastError();
+}
+
+hipError_t launch_chain_obs(const double *pos, const double *R, double *obs, double *m2,
+                            double *acc, const double *cm0, int M, int nch, int accumulate,
+                            hipStream_t st)
+{
+    if (nch == 0) return hipSuccess;
+    hipLaunchKernelGGL(chain_obs_kernel, dim3(nch), dim3(64), 0, st, pos, R, obs, m2, acc, cm0,
+                       M, accumulate);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_chains(const double *acc, double *out, int width, int nch,
+                                hipStream_t st)
+{
+    hipLaunchKernelGGL(reduce_chains_kernel, dim3(blocks_for(width, 256)), dim3(256), 0, st, acc,
+                       out, width, nch);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_finite_f64(const double *x, size_t n, int *flag, hipStream_t st)
+{
+    if (n == 0) return hipSuccess;
+    unsigned b = blocks_for(n, 256);
+    if (b > 2048) b = 2048;
+    hipLaunchKernelGGL(check_finite_kernel<double>, dim3(b), dim3(256), 0, st, x, n, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_finite_f32(const float *x, size_t n, int *flag, hipStream_t st)
+{
+    if (n == 0) return hipSuccess;
+    unsigned b = blocks_for(n, 256);
+    if (b > 2048) b = 2048;
+    hipLaunchKernelGGL(check_finite_kernel<float>, dim3(b), dim3(256), 0, st, x, n, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter_chains(const double *src, double *dst, const int64_t *off, int len,
+                                 int nch, hipStream_t st)
+{
+    const size_t n = (size_t)nch * len;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(scatter_chains_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, src,
+                       dst, off, len, nch);
+    return hipGetLastError();
+}
+
+}  // namespace dm

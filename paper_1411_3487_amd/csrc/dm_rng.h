@@ -1,0 +1,107 @@
+// dm_rng.h -- counter-based Gaussian noise for the Langevin steps.
+//
+// Philox4x32-10 (Salmon, Moraes, Dror & Shaw, "Parallel random numbers: as
+// easy as 1, 2, 3", SC'11): ten rounds of two 32x32->64 multiplies and xors
+// on a 128-bit counter, key schedule by the Weyl constants.  Box-Muller
+// (1958) turns the four 32-bit outputs into four standard normals.
+//
+// Counter convention (shared with the C ABI documentation):
+//   key     = (seed lo, seed hi)
+//   counter = (index / 4, chain, step lo, (step hi << 8) | (comp << 4) | tag)
+// and normal j of a block belongs to index 4 * (index / 4) + j.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dm {
+
+enum : uint32_t { kTagMode = 0u, kTagEuler = 1u };
+
+struct Block4 {
+    uint32_t v[4];
+};
+
+__host__ __device__ __forceinline__ uint32_t mul_hi32(uint32_t a, uint32_t b)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __umulhi(a, b);
+#else
+    return (uint32_t)(((uint64_t)a * (uint64_t)b) >> 32);
+#endif
+}
+
+__host__ __device__ __forceinline__ Block4 philox4x32_10(uint32_t c0, uint32_t c1,
+                                                         uint32_t c2, uint32_t c3,
+                                                         uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint32_t a_lo = c0 * 0xD2511F53u, a_hi = mul_hi32(c0, 0xD2511F53u);
+        const uint32_t b_lo = c2 * 0xCD9E8D57u, b_hi = mul_hi32(c2, 0xCD9E8D57u);
+        const uint32_t n0 = b_hi ^ c1 ^ k0;
+        const uint32_t n2 = a_hi ^ c3 ^ k1;
+        c0 = n0;
+        c1 = b_lo;
+        c2 = n2;
+        c3 = a_lo;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    Block4 out;
+    out.v[0] = c0;
+    out.v[1] = c1;
+    out.v[2] = c2;
+    out.v[3] = c3;
+    return out;
+}
+
+__host__ __device__ __forceinline__ Block4 noise_bits(uint64_t seed, uint32_t block,
+                                                      uint32_t chain, int64_t step,
+                                                      uint32_t comp, uint32_t tag)
+{
+    const uint64_t k = (uint64_t)step;
+    return philox4x32_10(block, chain, (uint32_t)k,
+                         ((uint32_t)(k >> 32) << 8) | (comp << 4) | tag,
+                         (uint32_t)seed, (uint32_t)(seed >> 32));
+}
+
+// Four N(0,1) in FP64: uniforms (x + 1/2) 2^-32, two Box-Muller pairs.
+__host__ __device__ __forceinline__ void normals4_f64(const Block4 &b, double z[4])
+{
+    const double scale = 2.3283064365386962890625e-10;  // 2^-32
+    const double two_pi = 6.283185307179586476925286766559;
+    const double u0 = ((double)b.v[0] + 0.5) * scale;
+    const double u1 = ((double)b.v[1] + 0.5) * scale;
+    const double u2 = ((double)b.v[2] + 0.5) * scale;
+    const double u3 = ((double)b.v[3] + 0.5) * scale;
+    const double ra = sqrt(-2.0 * log(u0));
+    const double rb = sqrt(-2.0 * log(u2));
+    z[0] = ra * cos(two_pi * u1);
+    z[1] = ra * sin(two_pi * u1);
+    z[2] = rb * cos(two_pi * u3);
+    z[3] = rb * sin(two_pi * u3);
+}
+
+#if defined(__HIP_DEVICE_COMPILE__) || defined(__HIPCC__)
+// Four N(0,1) in FP32 from the same bits, with the hardware transcendentals:
+// uniforms (x/256 + 1/2) 2^-24 (24 significant bits, never 0 or 1),
+// v_log_f32 (log2), v_sqrt_f32, and v_sin/v_cos_f32, which take their
+// argument in revolutions, so sin(2 pi u) = sin_rev(u).
+__device__ __forceinline__ void normals4_f32(const Block4 &b, float z[4])
+{
+    const float scale = 5.9604644775390625e-8f;  // 2^-24
+    const float m2ln2 = -1.3862943611198906f;    // -2 ln 2
+    const float u0 = ((float)(b.v[0] >> 8) + 0.5f) * scale;
+    const float u1 = ((float)(b.v[1] >> 8) + 0.5f) * scale;
+    const float u2 = ((float)(b.v[2] >> 8) + 0.5f) * scale;
+    const float u3 = ((float)(b.v[3] >> 8) + 0.5f) * scale;
+    const float ra = __builtin_amdgcn_sqrtf(m2ln2 * __builtin_amdgcn_logf(u0));
+    const float rb = __builtin_amdgcn_sqrtf(m2ln2 * __builtin_amdgcn_logf(u2));
+    z[0] = ra * __builtin_amdgcn_cosf(u1);
+    z[1] = ra * __builtin_amdgcn_sinf(u1);
+    z[2] = rb * __builtin_amdgcn_cosf(u3);
+    z[3] = rb * __builtin_amdgcn_sinf(u3);
+}
+#endif
+
+}  // namespace dm

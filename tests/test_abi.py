@@ -1,0 +1,67 @@
+"""CPU-side checks of the C ABI: the library loads, exports every symbol the
+header declares, and rejects bad arguments before touching the GPU."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1411_3487_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dnamodes.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(dm_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib.load()
+    names = declared_functions()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(_lib.EXPORTS)
+
+
+def test_header_constants_match_binding():
+    src = open(HEADER).read()
+    consts = dict(re.findall(r"#define\s+(DM_[A-Z0-9_]+)\s+(-?\d+)", src))
+    for name in ["DM_OK", "DM_EINVAL", "DM_ENOMEM", "DM_EHIP", "DM_ENONFINITE", "DM_ESTATE",
+                 "DM_FP64", "DM_FP32", "DM_BF16X3", "DM_OBS_CHAIN", "DM_OBS_MODES",
+                 "DM_OBS_ACCUM", "DM_OBS_RESET", "DM_NCHAIN_OBS", "DM_NACC_HEAD"]:
+        assert int(consts[name]) == getattr(_lib, name), name
+    assert len(_lib.CHAIN_OBS_NAMES) == _lib.DM_NCHAIN_OBS
+    assert len(_lib.ACC_NAMES) == _lib.DM_NACC_HEAD
+
+
+def test_params_struct_layout():
+    # 8 doubles, 2 int32, 2 pointers, 2 int32 (natural alignment, x86-64)
+    assert ctypes.sizeof(_lib.dm_params) == 8 * 8 + 8 + 16 + 8
+
+
+@pytest.mark.parametrize("n,beads,prec", [(0, [64], 0), (1, [1], 0), (1, [64], 7),
+                                          (1, [63], 1), (1, [514], 2), (1, [3000], 0)])
+def test_init_rejects_bad_arguments_without_gpu(n, beads, prec):
+    lib = _lib.load()
+    h = ctypes.c_void_p()
+    b = np.array(beads, dtype=np.int32)
+    pos = np.zeros(3 * int(b.sum()) + 3)
+    rc = lib.dm_init_chains(ctypes.byref(h), n, b.ctypes.data, pos.ctypes.data, 0, prec, None)
+    assert rc == _lib.DM_EINVAL
+    assert not h.value
+    assert len(lib.dm_last_error(None)) > 0
+
+
+def test_null_pointers_are_rejected():
+    lib = _lib.load()
+    h = ctypes.c_void_p()
+    b = np.array([64], dtype=np.int32)
+    assert lib.dm_init_chains(ctypes.byref(h), 1, b.ctypes.data, None, 0, 0, None) == _lib.DM_EINVAL
+    assert lib.dm_init_chains(None, 1, b.ctypes.data, None, 0, 0, None) == _lib.DM_EINVAL
+    assert lib.dm_step_modes(None, 1) == _lib.DM_EINVAL
+    assert lib.dm_destroy(None) == _lib.DM_EINVAL
