@@ -53,7 +53,7 @@ struct FusedArgs {
     double *R0;
     const float *coef;
     const int32_t *ids;
-    int M, H, n, ntiles;
+    int M, H, n, ntiles, x_bytes;
     uint64_t seed;
     int64_t step0;
     int n_steps, nonlinear;
@@ -61,28 +61,26 @@ struct FusedArgs {
     double W0, gdt;
 };
 
-// Sum of v over the three component lanes of this lane's chain
-// (columns 3c, 3c+1, 3c+2 of a 16-lane row); alpha = column % 3.
-__device__ __forceinline__ float comp_sum(float v, int lane, int alpha)
+// DPP lane moves inside a 16-lane row (out-of-row sources read 0):
+// row_shl:n gives lane i the value of lane i+n, row_shr:n that of lane i-n.
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v)
 {
-    const float a = __shfl(v, (lane + 1) & 63, 64);
-    const float b = __shfl(v, (lane + 2) & 63, 64);
-    const float s = v + a + b;  // complete in the alpha == 0 lane
-    return __shfl(s, lane - alpha, 64);
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+constexpr int kRowShl1 = 0x101, kRowShl2 = 0x102, kRowShr1 = 0x111, kRowShr2 = 0x112;
+
+// Sum of v over the three component lanes of this lane's chain (columns 3c,
+// 3c+1, 3c+2 of a 16-lane row); alpha = column % 3.
+__device__ __forceinline__ float comp_sum(float v, int alpha)
+{
+    const float s = v + dpp<kRowShl1>(v) + dpp<kRowShl2>(v);  // complete at alpha == 0
+    const float s1 = dpp<kRowShr1>(s), s2 = dpp<kRowShr2>(s);
+    return alpha == 0 ? s : (alpha == 1 ? s1 : s2);
 }
 
-// The transform tables do not change between steps; without this the
-// compiler hoists every table load out of the step loop into registers and
-// spills.  Adding an opaque zero at each use site keeps the loads in place
-// (and in the global address space).
-template <typename T>
-__device__ __forceinline__ const T *opaque(const T *p)
-{
-    int zero = 0;
-    asm volatile("" : "+s"(zero));
-    return p + zero;
-}
-
+// x = hi + lo with hi = bf16(x) and lo = bf16(x - hi), for the 8 K-slots of
+// a slab made of two 16-row result tiles.
 __device__ __forceinline__ void split_bf16(const f32x4 lo4, const f32x4 hi4, bf16x8 &h, bf16x8 &l)
 {
 #pragma unroll
@@ -94,186 +92,269 @@ __device__ __forceinline__ void split_bf16(const f32x4 lo4, const f32x4 hi4, bf1
     }
 }
 
+__device__ __forceinline__ f32x4 mfma_bf16(bf16x8 a, bf16x8 b, f32x4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f32x4 mfma_f32(float a, float b, f32x4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// Bond force of the half-bond rows of one 16-row tile: G+ = g_i + g_{M-i},
+// G- = g_i - g_{M-i}, g = u (1/|u| - lin).  No masks are needed: padding rows,
+// padding columns and the antisymmetric part of the middle bond are exactly
+// zero (u = 0 gives g = 0 thanks to the tiny offset under the rsqrt), and the
+// middle bond, which enters G+ twice, has its coupling column halved in the
+// table.
+__device__ __forceinline__ void bond_forces(const f32x4 aS, const f32x4 aA, int alpha, float lin,
+                                            f32x4 &Gp, f32x4 &Gm)
+{
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const float up = aS[r] + aA[r], um = aS[r] - aA[r];
+        const float sp = comp_sum(up * up, alpha);
+        const float sm = comp_sum(um * um, alpha);
+        const float gp = up * (__builtin_amdgcn_rsqf(sp + 1e-30f) - lin);
+        const float gm = um * (__builtin_amdgcn_rsqf(sm + 1e-30f) - lin);
+        Gp[r] = gp + gm;
+        Gm[r] = gp - gm;
+    }
+}
+
+// One K slab (32 rows) of the transform tables: 4 * RT fragments of 1 KB in
+// global memory, copied to LDS by the whole workgroup with buffer loads that
+// write LDS directly (16 bytes per lane, no register staging).  All address
+// arithmetic is scalar: one buffer descriptor, the slab and fragment byte
+// offsets in SGPRs, the lane offset in one VGPR.
+template <int RT>
+__device__ __forceinline__ void stage_slab(__amdgpu_buffer_rsrc_t rs, int slab, f32x4 *dst,
+                                           int wave, int lane_bytes)
+{
+#pragma unroll
+    for (int f = 0; f < RT; ++f) {
+        const int fr = 4 * f + wave;  // fragment of this wave
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(
+            rs, (__attribute__((address_space(3))) void *)(dst + fr * 64), 16, lane_bytes,
+            (slab * 4 * RT + fr) * 1024, 0, 0);
+    }
+}
+
+// Value of x that the compiler must treat as depending on d: used to keep
+// the noise generation of a mode tile after the work it would otherwise be
+// hoisted above (which would keep all normals of a step live at once).
+__device__ __forceinline__ uint32_t after(uint32_t x, float d)
+{
+    asm("" : "+v"(x) : "v"(d));
+    return x;
+}
+
+// Fused stepper.  Workgroup = 4 wavefronts = 4 tiles of 5 chains; the
+// transform tables stream through a double-buffered LDS slab shared by all
+// four tiles, so each table byte crosses L2 once per workgroup and step.
+// Table layout: [gemm (2)][slab q (RT/2)][row tile (RT)][fragment f (4)][lane]
+// with 16-byte fragments: BF16 f = (odd hi, odd lo, even hi, even lo) of one
+// K = 32 slab; FP32 f = (odd t=2q, odd t=2q+1, even t=2q, even t=2q+1), each
+// four K = 4 slices.
 template <int RT, bool BF16>
 __global__ __launch_bounds__(256) void fused_kernel(FusedArgs a)
 {
+    constexpr int KS = RT / 2;
+    constexpr int SLAB = 4 * RT * 64;  // f32x4 per slab
     __shared__ float cf[4 * 32 * RT];  // E, C, W, gdt*E per mode slot
-    for (int i = threadIdx.x; i < 4 * 32 * RT; i += blockDim.x) cf[i] = a.coef[i];
-    __syncthreads();
-    const float *cE = cf, *cC = cf + 32 * RT, *cW = cf + 64 * RT, *cS = cf + 96 * RT;
-
+    __shared__ f32x4 xb[2][SLAB];
     const int lane = threadIdx.x & 63;
-    const int tile = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (tile >= a.ntiles) return;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (int i = threadIdx.x; i < 4 * 32 * RT; i += blockDim.x) cf[i] = a.coef[i];
+
+    const int tile = blockIdx.x * 4 + wave;
+    const bool has_tile = tile < a.ntiles;  // idle waves still stage and sync
     const int col = lane & 15, g = lane >> 4;
     const int cl = col / 3, alpha = col - 3 * cl;
-    const int nvalid = min(kChainsPerTile, a.n - kChainsPerTile * tile);
+    const int nvalid = has_tile ? min(kChainsPerTile, a.n - kChainsPerTile * tile) : 0;
     const bool valid = (col < 15) && (cl < nvalid);
     const uint32_t chain = valid ? (uint32_t)a.ids[kChainsPerTile * tile + cl] : 0u;
-    const float vmask = valid ? 1.0f : 0.0f;
+    const __amdgpu_buffer_rsrc_t xrs =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(a.X), 0, a.x_bytes, 0x00020000);
+    const int lane_bytes = lane * 16;
 
     f32x4 Ro[RT], Re[RT];
     const f32x4 *Rt = reinterpret_cast<const f32x4 *>(a.R) + (size_t)tile * 2 * RT * 64;
 #pragma unroll
     for (int t = 0; t < RT; ++t) {
-        Ro[t] = Rt[(0 * RT + t) * 64 + lane];
-        Re[t] = Rt[(1 * RT + t) * 64 + lane];
+        Ro[t] = has_tile ? Rt[(0 * RT + t) * 64 + lane] : f32x4{0.f, 0.f, 0.f, 0.f};
+        Re[t] = has_tile ? Rt[(1 * RT + t) * 64 + lane] : f32x4{0.f, 0.f, 0.f, 0.f};
     }
     const bool com_lane = valid && g == 0;
+    const float xlane = alpha == 0 ? 1.0f : 0.0f;  // lanes holding x components
     double r0 = com_lane ? a.R0[(size_t)tile * 16 + col] : 0.0;
+
+    int buf = 0;
+    if (a.nonlinear) {
+        stage_slab<RT>(xrs, 0, xb[0], wave, lane_bytes);
+        __builtin_amdgcn_s_waitcnt(0);
+    }
+    __syncthreads();
 
     for (int s = 0; s < a.n_steps; ++s) {
         const int64_t k = a.step0 + s;
-        // ---------------- bond forces: G+ / G- over half-bond rows
-        f32x4 Gp[RT], Gm[RT];
-        if (a.nonlinear) {
-            if constexpr (BF16) {
-                constexpr int KS = RT / 2, TS = RT * KS * 64;
-                bf16x8 Boh[KS], Bol[KS], Beh[KS], Bel[KS];
+        f32x4 dO[RT], dE[RT];
+        if (!a.nonlinear) {
 #pragma unroll
-                for (int q = 0; q < KS; ++q) {
-                    split_bf16(Ro[2 * q], Ro[2 * q + 1], Boh[q], Bol[q]);
-                    split_bf16(Re[2 * q], Re[2 * q + 1], Beh[q], Bel[q]);
-                }
-#pragma unroll
-                for (int I = 0; I < RT; ++I) {
-                    const bf16x8 *X1 = opaque(reinterpret_cast<const bf16x8 *>(a.X));
-                    f32x4 aS = {0.f, 0.f, 0.f, 0.f}, aA = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                    for (int q = 0; q < KS; ++q) {
-                        const int off = (I * KS + q) * 64 + lane;
-                        const bf16x8 xoh = X1[0 * TS + off], xol = X1[1 * TS + off];
-                        const bf16x8 xeh = X1[2 * TS + off], xel = X1[3 * TS + off];
-                        aS = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xoh, Boh[q], aS, 0, 0, 0);
-                        aA = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xeh, Beh[q], aA, 0, 0, 0);
-                        aS = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xoh, Bol[q], aS, 0, 0, 0);
-                        aA = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xeh, Bel[q], aA, 0, 0, 0);
-                        aS = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xol, Boh[q], aS, 0, 0, 0);
-                        aA = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xel, Beh[q], aA, 0, 0, 0);
-                    }
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int i = 16 * I + 4 * g + r;
-                        const float up = aS[r] + aA[r], um = aS[r] - aA[r];
-                        const float sp = comp_sum(up * up, lane, alpha);
-                        const float sm = comp_sum(um * um, lane, alpha);
-                        const float gp = up * (__builtin_amdgcn_rsqf(sp) - a.lin);
-                        const float gm = um * (__builtin_amdgcn_rsqf(sm) - a.lin);
-                        const bool ok = valid && i < a.H;
-                        const bool mid = (i == a.H - 1);
-                        Gp[I][r] = ok ? (mid ? gp : gp + gm) : 0.0f;
-                        Gm[I][r] = (ok && !mid) ? gp - gm : 0.0f;
-                    }
-                }
-            } else {
-                constexpr int TS = RT * RT * 64;
-#pragma unroll
-                for (int I = 0; I < RT; ++I) {
-                    const f32x4 *X1 = opaque(reinterpret_cast<const f32x4 *>(a.X));
-                    f32x4 aS = {0.f, 0.f, 0.f, 0.f}, aA = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                    for (int t = 0; t < RT; ++t) {
-                        const int off = (I * RT + t) * 64 + lane;
-                        const f32x4 xo = X1[0 * TS + off], xe = X1[1 * TS + off];
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) {
-                            aS = __builtin_amdgcn_mfma_f32_16x16x4f32(xo[r], Ro[t][r], aS, 0, 0, 0);
-                            aA = __builtin_amdgcn_mfma_f32_16x16x4f32(xe[r], Re[t][r], aA, 0, 0, 0);
-                        }
-                    }
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int i = 16 * I + 4 * g + r;
-                        const float up = aS[r] + aA[r], um = aS[r] - aA[r];
-                        const float sp = comp_sum(up * up, lane, alpha);
-                        const float sm = comp_sum(um * um, lane, alpha);
-                        const float gp = up * (__builtin_amdgcn_rsqf(sp) - a.lin);
-                        const float gm = um * (__builtin_amdgcn_rsqf(sm) - a.lin);
-                        const bool ok = valid && i < a.H;
-                        const bool mid = (i == a.H - 1);
-                        Gp[I][r] = ok ? (mid ? gp : gp + gm) : 0.0f;
-                        Gm[I][r] = (ok && !mid) ? gp - gm : 0.0f;
-                    }
-                }
+            for (int J = 0; J < RT; ++J) {
+                dO[J] = f32x4{0.f, 0.f, 0.f, 0.f};
+                dE[J] = f32x4{0.f, 0.f, 0.f, 0.f};
             }
-        }
-        // ---------------- coupling per mode tile J, then the mode update
-        [[maybe_unused]] bf16x8 Gph[RT / 2], Gpl[RT / 2], Gmh[RT / 2], Gml[RT / 2];
-        if constexpr (BF16) {
-            if (a.nonlinear) {
+        } else {
+            // ---- u = chi R: half-bond rows I, K over mode slabs q
+            f32x4 aS[RT], aA[RT];
 #pragma unroll
-                for (int q = 0; q < RT / 2; ++q) {
-                    split_bf16(Gp[2 * q], Gp[2 * q + 1], Gph[q], Gpl[q]);
-                    split_bf16(Gm[2 * q], Gm[2 * q + 1], Gmh[q], Gml[q]);
-                }
+            for (int I = 0; I < RT; ++I) {
+                aS[I] = f32x4{0.f, 0.f, 0.f, 0.f};
+                aA[I] = f32x4{0.f, 0.f, 0.f, 0.f};
             }
-        }
 #pragma unroll
-        for (int J = 0; J < RT; ++J) {
-            f32x4 dO = {0.f, 0.f, 0.f, 0.f}, dE = {0.f, 0.f, 0.f, 0.f};
-            if (a.nonlinear) {
+            for (int q = 0; q < KS; ++q) {
+                // prefetch the next slab: next q of this product, else the
+                // first slab of the coupling product
+                const int nq = (q + 1 < KS) ? (q + 1) : KS;
+                stage_slab<RT>(xrs, nq, xb[buf ^ 1], wave, lane_bytes);
+                const f32x4 *xs = xb[buf];
                 if constexpr (BF16) {
-                    constexpr int KS = RT / 2, TS = RT * KS * 64;
-                    const bf16x8 *X2 = opaque(reinterpret_cast<const bf16x8 *>(a.X)) + 4 * TS;
-#pragma unroll
-                    for (int q = 0; q < KS; ++q) {
-                        const int off = (J * KS + q) * 64 + lane;
-                        const bf16x8 xoh = X2[0 * TS + off], xol = X2[1 * TS + off];
-                        const bf16x8 xeh = X2[2 * TS + off], xel = X2[3 * TS + off];
-                        dO = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xoh, Gph[q], dO, 0, 0, 0);
-                        dE = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xeh, Gmh[q], dE, 0, 0, 0);
-                        dO = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xoh, Gpl[q], dO, 0, 0, 0);
-                        dE = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xeh, Gml[q], dE, 0, 0, 0);
-                        dO = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xol, Gph[q], dO, 0, 0, 0);
-                        dE = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xel, Gmh[q], dE, 0, 0, 0);
-                    }
-                } else {
-                    constexpr int TS = RT * RT * 64;
-                    const f32x4 *X2 = opaque(reinterpret_cast<const f32x4 *>(a.X)) + 2 * TS;
+                    bf16x8 boh, bol, beh, bel;
+                    split_bf16(Ro[2 * q], Ro[2 * q + 1], boh, bol);
+                    split_bf16(Re[2 * q], Re[2 * q + 1], beh, bel);
 #pragma unroll
                     for (int I = 0; I < RT; ++I) {
-                        const int off = (J * RT + I) * 64 + lane;
-                        const f32x4 xo = X2[0 * TS + off], xe = X2[1 * TS + off];
+                        const f32x4 *fr = xs + (I * 4) * 64 + lane;
+                        const bf16x8 xoh = __builtin_bit_cast(bf16x8, fr[0]);
+                        const bf16x8 xol = __builtin_bit_cast(bf16x8, fr[64]);
+                        const bf16x8 xeh = __builtin_bit_cast(bf16x8, fr[128]);
+                        const bf16x8 xel = __builtin_bit_cast(bf16x8, fr[192]);
+                        aS[I] = mfma_bf16(xoh, boh, aS[I]);
+                        aA[I] = mfma_bf16(xeh, beh, aA[I]);
+                        aS[I] = mfma_bf16(xoh, bol, aS[I]);
+                        aA[I] = mfma_bf16(xeh, bel, aA[I]);
+                        aS[I] = mfma_bf16(xol, boh, aS[I]);
+                        aA[I] = mfma_bf16(xel, beh, aA[I]);
+                    }
+                } else {
 #pragma unroll
-                        for (int r = 0; r < 4; ++r) {
-                            dO = __builtin_amdgcn_mfma_f32_16x16x4f32(xo[r], Gp[I][r], dO, 0, 0, 0);
-                            dE = __builtin_amdgcn_mfma_f32_16x16x4f32(xe[r], Gm[I][r], dE, 0, 0, 0);
+                    for (int I = 0; I < RT; ++I) {
+                        const f32x4 *fr = xs + (I * 4) * 64 + lane;
+#pragma unroll
+                        for (int h = 0; h < 2; ++h) {
+                            const f32x4 xo = fr[h * 64], xe = fr[(2 + h) * 64];
+#pragma unroll
+                            for (int r = 0; r < 4; ++r) {
+                                aS[I] = mfma_f32(xo[r], Ro[2 * q + h][r], aS[I]);
+                                aA[I] = mfma_f32(xe[r], Re[2 * q + h][r], aA[I]);
+                            }
                         }
                     }
                 }
+                __builtin_amdgcn_s_waitcnt(0);
+                __syncthreads();
+                buf ^= 1;
             }
-            // modes of this lane: p = 32J + 8g + m, m = 0..7; even p = .. + 2r
-            // sits in Re[J][r], odd p = .. + 2r + 1 in Ro[J][r]
+            // ---- bond forces
+            f32x4 Gp[RT], Gm[RT];
+#pragma unroll
+            for (int I = 0; I < RT; ++I)
+                bond_forces(aS[I], aA[I], alpha, a.lin, Gp[I], Gm[I]);
+            // ---- Delta H = chi^T g: mode rows J, K over half-bond slabs q
+#pragma unroll
+            for (int J = 0; J < RT; ++J) {
+                dO[J] = f32x4{0.f, 0.f, 0.f, 0.f};
+                dE[J] = f32x4{0.f, 0.f, 0.f, 0.f};
+            }
+#pragma unroll
+            for (int q = 0; q < KS; ++q) {
+                if (q + 1 < KS)
+                    stage_slab<RT>(xrs, KS + q + 1, xb[buf ^ 1], wave, lane_bytes);
+                else if (s + 1 < a.n_steps)
+                    stage_slab<RT>(xrs, 0, xb[buf ^ 1], wave, lane_bytes);
+                const f32x4 *xs = xb[buf];
+                if constexpr (BF16) {
+                    bf16x8 gph, gpl, gmh, gml;
+                    split_bf16(Gp[2 * q], Gp[2 * q + 1], gph, gpl);
+                    split_bf16(Gm[2 * q], Gm[2 * q + 1], gmh, gml);
+#pragma unroll
+                    for (int J = 0; J < RT; ++J) {
+                        const f32x4 *fr = xs + (J * 4) * 64 + lane;
+                        const bf16x8 xoh = __builtin_bit_cast(bf16x8, fr[0]);
+                        const bf16x8 xol = __builtin_bit_cast(bf16x8, fr[64]);
+                        const bf16x8 xeh = __builtin_bit_cast(bf16x8, fr[128]);
+                        const bf16x8 xel = __builtin_bit_cast(bf16x8, fr[192]);
+                        dO[J] = mfma_bf16(xoh, gph, dO[J]);
+                        dE[J] = mfma_bf16(xeh, gmh, dE[J]);
+                        dO[J] = mfma_bf16(xoh, gpl, dO[J]);
+                        dE[J] = mfma_bf16(xeh, gml, dE[J]);
+                        dO[J] = mfma_bf16(xol, gph, dO[J]);
+                        dE[J] = mfma_bf16(xel, gmh, dE[J]);
+                    }
+                } else {
+#pragma unroll
+                    for (int J = 0; J < RT; ++J) {
+                        const f32x4 *fr = xs + (J * 4) * 64 + lane;
+#pragma unroll
+                        for (int h = 0; h < 2; ++h) {
+                            const f32x4 xo = fr[h * 64], xe = fr[(2 + h) * 64];
+#pragma unroll
+                            for (int r = 0; r < 4; ++r) {
+                                dO[J] = mfma_f32(xo[r], Gp[2 * q + h][r], dO[J]);
+                                dE[J] = mfma_f32(xe[r], Gm[2 * q + h][r], dE[J]);
+                            }
+                        }
+                    }
+                }
+                __builtin_amdgcn_s_waitcnt(0);
+                __syncthreads();
+                buf ^= 1;
+            }
+        }
+        // ---- mode update: lane holds p = 32J + 8g + m, m = 0..7; even p =
+        // .. + 2r in Re[J][r], odd p = .. + 2r + 1 in Ro[J][r]
+#pragma unroll
+        for (int J = 0; J < RT; ++J) {
+            // noise of tile J only after the coupling of tile J and the
+            // update of tile J-1
+            const uint32_t ch = after(after(chain, dO[J][0]), J ? Ro[J - 1][3] : dE[J][0]);
             float z[8];
-            normals4_f32(noise_bits(a.seed, (uint32_t)(8 * J + 2 * g), chain, k, (uint32_t)alpha,
+            normals4_f32(noise_bits(a.seed, (uint32_t)(8 * J + 2 * g), ch, k, (uint32_t)alpha,
                                     kTagMode),
                          z);
-            normals4_f32(noise_bits(a.seed, (uint32_t)(8 * J + 2 * g + 1), chain, k,
+            normals4_f32(noise_bits(a.seed, (uint32_t)(8 * J + 2 * g + 1), ch, k,
                                     (uint32_t)alpha, kTagMode),
                          z + 4);
-            // opaque zero: keeps the coefficient reads inside the step loop
-            int cb = (J * 4 + g) * 8;
-            asm volatile("" : "+v"(cb));
-            f32x4 ye = {0.f, 0.f, 0.f, 0.f}, yo = {0.f, 0.f, 0.f, 0.f};
+            const int cb = (J * 4 + g) * 8;
+            f32x4 ye, yo;
             if (a.gdt != 0.0) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    ye[r] = __shfl(Re[J][r], (lane + 1) & 63, 64);
-                    yo[r] = __shfl(Ro[J][r], (lane + 1) & 63, 64);
+                    // R^y of the same chain, for the x lanes only.  The lane
+                    // move runs with every lane active (a DPP read from a lane
+                    // masked off by a branch returns 0), then is masked.
+                    ye[r] = xlane * dpp<kRowShl1>(Re[J][r]);
+                    yo[r] = xlane * dpp<kRowShl1>(Ro[J][r]);
                 }
             }
-            const float shear = alpha == 0 ? 1.0f : 0.0f;
+            // Columns without a chain evolve like free chains that start at
+            // zero; product columns are independent, so they never touch the
+            // real chains, and they are not written back.
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int me = cb + 2 * r, mo = me + 1;
-                float ve = cE[me] * Re[J][r] + cW[me] * z[2 * r];
-                float vo = cE[mo] * Ro[J][r] + cW[mo] * z[2 * r + 1];
-                ve += cC[me] * dE[r];
-                vo += cC[mo] * dO[r];
-                ve += shear * cS[me] * ye[r];
-                vo += shear * cS[mo] * yo[r];
-                Re[J][r] = vmask * ve;
-                Ro[J][r] = vmask * vo;
+                float ve = cf[me] * Re[J][r] + cf[64 * RT + me] * z[2 * r];
+                float vo = cf[mo] * Ro[J][r] + cf[64 * RT + mo] * z[2 * r + 1];
+                ve += cf[32 * RT + me] * dE[J][r];
+                vo += cf[32 * RT + mo] * dO[J][r];
+                if (a.gdt != 0.0) {
+                    ve += cf[96 * RT + me] * ye[r];
+                    vo += cf[96 * RT + mo] * yo[r];
+                }
+                Re[J][r] = ve;
+                Ro[J][r] = vo;
             }
             if (J == 0) {
                 // centre of mass (p = 0, slot m = 0 of the g = 0 lanes): free
@@ -285,6 +366,7 @@ __global__ __launch_bounds__(256) void fused_kernel(FusedArgs a)
             }
         }
     }
+    if (!has_tile) return;
     f32x4 *Rw = reinterpret_cast<f32x4 *>(a.R) + (size_t)tile * 2 * RT * 64;
 #pragma unroll
     for (int t = 0; t < RT; ++t) {
@@ -395,46 +477,47 @@ hipError_t fused_alloc(FusedBucket &f, int M, int n, bool bf16, const std::vecto
         return e;
     if ((e = hipMalloc((void **)&f.d_coef, sizeof(float) * 128 * (size_t)RT)) != hipSuccess)
         return e;
+    // fragment order [gemm][slab q][row tile A][f][lane][16 bytes], see fused_kernel
     const double *src[2] = {Xo.data(), Xe.data()};
+    const int KS = RT / 2;
+    auto at = [&](int kind, int row, int colx) { return src[kind][(size_t)row * Hp + colx]; };
     if (!bf16) {
-        // GEMM1 (I, t, lane, r): X[16I + lane%16][16t + 4(lane/16) + r]
-        // GEMM2 (J, I, lane, r): X[16I + 4(lane/16) + r][16J + lane%16]
-        std::vector<float> h((size_t)4 * RT * RT * 256);
-        const size_t TS = (size_t)RT * RT * 256;
-        for (int kind = 0; kind < 2; ++kind)
-            for (int A = 0; A < RT; ++A)
-                for (int B = 0; B < RT; ++B)
-                    for (int l = 0; l < 64; ++l)
-                        for (int r = 0; r < 4; ++r) {
-                            const size_t o = (((size_t)A * RT + B) * 64 + l) * 4 + r;
-                            const int lo = l % 16, hi = 4 * (l / 16) + r;
-                            h[kind * TS + o] = (float)src[kind][(size_t)(16 * A + lo) * Hp + 16 * B + hi];
-                            h[(2 + kind) * TS + o] =
-                                (float)src[kind][(size_t)(16 * B + hi) * Hp + 16 * A + lo];
-                        }
+        std::vector<float> h((size_t)2 * KS * RT * 4 * 64 * 4);
+        for (int gm = 0; gm < 2; ++gm)
+            for (int q = 0; q < KS; ++q)
+                for (int A = 0; A < RT; ++A)
+                    for (int fr = 0; fr < 4; ++fr)
+                        for (int l = 0; l < 64; ++l)
+                            for (int r = 0; r < 4; ++r) {
+                                const int kind = fr / 2, t = 2 * q + (fr % 2);
+                                const int lo = l % 16, kk = 16 * t + 4 * (l / 16) + r;
+                                // GEMM1: A[i = 16A + lo][k]; GEMM2: X^T, A[j = 16A + lo][k]
+                                double v = gm == 0 ? at(kind, 16 * A + lo, kk)
+                                                   : at(kind, kk, 16 * A + lo);
+                                if (gm == 1 && kk == H - 1) v *= 0.5;  // middle bond, see bond_forces
+                                h[(((((size_t)gm * KS + q) * RT + A) * 4 + fr) * 64 + l) * 4 + r] =
+                                    (float)v;
+                            }
         e = hipMemcpy(f.d_X, h.data(), xb, hipMemcpyHostToDevice);
     } else {
-        // slabs of K = 32: GEMM1 (I, q, lane, e): X[16I + lane%16][k(q, lane/16, e)]
-        //                  GEMM2 (J, q, lane, e): X[k(q, lane/16, e)][16J + lane%16]
-        // tables in the order [GEMM1 o hi, o lo, e hi, e lo, GEMM2 o hi, o lo, e hi, e lo]
-        const int KS = RT / 2;
-        const size_t TS = (size_t)RT * KS * 512;
-        std::vector<__bf16> h(8 * TS);
-        for (int kind = 0; kind < 2; ++kind)
-            for (int A = 0; A < RT; ++A)
-                for (int q = 0; q < KS; ++q)
-                    for (int l = 0; l < 64; ++l)
-                        for (int el = 0; el < 8; ++el) {
-                            const size_t o = (((size_t)A * KS + q) * 64 + l) * 8 + el;
-                            const int kk = kslab_index(q, l / 16, el), lo = l % 16;
-                            const double v1 = src[kind][(size_t)(16 * A + lo) * Hp + kk];
-                            const double v2 = src[kind][(size_t)kk * Hp + 16 * A + lo];
-                            const __bf16 h1 = (__bf16)(float)v1, h2 = (__bf16)(float)v2;
-                            h[(2 * kind + 0) * TS + o] = h1;
-                            h[(2 * kind + 1) * TS + o] = (__bf16)(float)(v1 - (double)(float)h1);
-                            h[(4 + 2 * kind + 0) * TS + o] = h2;
-                            h[(4 + 2 * kind + 1) * TS + o] = (__bf16)(float)(v2 - (double)(float)h2);
-                        }
+        std::vector<__bf16> h((size_t)2 * KS * RT * 4 * 64 * 8);
+        for (int gm = 0; gm < 2; ++gm)
+            for (int q = 0; q < KS; ++q)
+                for (int A = 0; A < RT; ++A)
+                    for (int fr = 0; fr < 4; ++fr)
+                        for (int l = 0; l < 64; ++l)
+                            for (int el = 0; el < 8; ++el) {
+                                const int kind = fr / 2, part = fr % 2;  // hi, lo
+                                const int lo = l % 16, kk = kslab_index(q, l / 16, el);
+                                double v = gm == 0 ? at(kind, 16 * A + lo, kk)
+                                                   : at(kind, kk, 16 * A + lo);
+                                if (gm == 1 && kk == H - 1) v *= 0.5;  // middle bond, see bond_forces
+                                const __bf16 vh = (__bf16)(float)v;
+                                const __bf16 out =
+                                    part == 0 ? vh : (__bf16)(float)(v - (double)(float)vh);
+                                h[(((((size_t)gm * KS + q) * RT + A) * 4 + fr) * 64 + l) * 8 + el] =
+                                    out;
+                            }
         e = hipMemcpy(f.d_X, h.data(), xb, hipMemcpyHostToDevice);
     }
     if (e != hipSuccess) return e;
@@ -515,6 +598,7 @@ hipError_t fused_step(FusedBucket &f, const int32_t *ids, int M, int n, uint64_t
     a.H = M / 2;
     a.n = n;
     a.ntiles = f.ntiles;
+    a.x_bytes = (int)x_bytes(f.RT, f.bf16 != 0);
     a.seed = seed;
     a.step0 = step0;
     a.n_steps = n_steps;

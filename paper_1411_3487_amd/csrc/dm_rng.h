@@ -21,12 +21,15 @@ struct Block4 {
     uint32_t v[4];
 };
 
-__host__ __device__ __forceinline__ uint32_t mul_hi32(uint32_t a, uint32_t b)
+// x ^ y ^ k in one VALU op on gfx950 (v_bitop3_b32, truth table 0x96).
+__host__ __device__ __forceinline__ uint32_t xor3(uint32_t x, uint32_t y, uint32_t k)
 {
 #if defined(__HIP_DEVICE_COMPILE__)
-    return __umulhi(a, b);
+    uint32_t r;
+    asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(r) : "v"(x), "v"(y), "s"(k));
+    return r;
 #else
-    return (uint32_t)(((uint64_t)a * (uint64_t)b) >> 32);
+    return x ^ y ^ k;
 #endif
 }
 
@@ -36,10 +39,13 @@ __host__ __device__ __forceinline__ Block4 philox4x32_10(uint32_t c0, uint32_t c
 {
 #pragma unroll
     for (int round = 0; round < 10; ++round) {
-        const uint32_t a_lo = c0 * 0xD2511F53u, a_hi = mul_hi32(c0, 0xD2511F53u);
-        const uint32_t b_lo = c2 * 0xCD9E8D57u, b_hi = mul_hi32(c2, 0xCD9E8D57u);
-        const uint32_t n0 = b_hi ^ c1 ^ k0;
-        const uint32_t n2 = a_hi ^ c3 ^ k1;
+        // full 32x32->64 products (one v_mad_u64_u32 each)
+        const uint64_t pa = (uint64_t)c0 * 0xD2511F53u;
+        const uint64_t pb = (uint64_t)c2 * 0xCD9E8D57u;
+        const uint32_t a_lo = (uint32_t)pa, a_hi = (uint32_t)(pa >> 32);
+        const uint32_t b_lo = (uint32_t)pb, b_hi = (uint32_t)(pb >> 32);
+        const uint32_t n0 = xor3(b_hi, c1, k0);
+        const uint32_t n2 = xor3(a_hi, c3, k1);
         c0 = n0;
         c1 = b_lo;
         c2 = n2;
