@@ -17,9 +17,12 @@ struct FusedBucket {
     void *d_X = nullptr;     // bond-mode transform fragments (see dm_fused.hip)
     float *d_R = nullptr;    // internal mode amplitudes, fragment order
     double *d_R0 = nullptr;  // centre-of-mass mode, ntiles * 16 doubles
-    float *d_coef = nullptr; // per-mode E, C, W, gdt*E in lane order
+    float *d_coef = nullptr; // per-mode E, W, gdt*E in lane order
+    int JC = 0;              // coupling row tiles with non-negligible C_p
     double W0 = 0.0, gdt = 0.0;
     float lin = 0.0f;
+    std::vector<double> Xo, Xe;  // host FP64 half tables (the coupling table
+                                 // is rebuilt with C_p whenever dtau changes)
 };
 
 bool fused_supports(int M);

@@ -33,6 +33,7 @@
 // The centre-of-mass mode R_0 (p = 0) is kept in FP64 in lanes 0..14.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -53,7 +54,7 @@ struct FusedArgs {
     double *R0;
     const float *coef;
     const int32_t *ids;
-    int M, H, n, ntiles, x_bytes;
+    int M, H, n, ntiles, x_bytes, jc;
     uint64_t seed;
     int64_t step0;
     int n_steps, nonlinear;
@@ -122,22 +123,33 @@ __device__ __forceinline__ void bond_forces(const f32x4 aS, const f32x4 aA, int 
     }
 }
 
-// One K slab (32 rows) of the transform tables: 4 * RT fragments of 1 KB in
-// global memory, copied to LDS by the whole workgroup with buffer loads that
-// write LDS directly (16 bytes per lane, no register staging).  All address
-// arithmetic is scalar: one buffer descriptor, the slab and fragment byte
-// offsets in SGPRs, the lane offset in one VGPR.
-template <int RT>
-__device__ __forceinline__ void stage_slab(__amdgpu_buffer_rsrc_t rs, int slab, f32x4 *dst,
-                                           int wave, int lane_bytes)
+// Copy nfrag consecutive 1 KB fragments of the transform tables, starting at
+// fragment first, to LDS: the whole workgroup issues buffer loads that write
+// LDS directly (16 bytes per lane, no register staging).  All address
+// arithmetic is scalar: one buffer descriptor, the byte offsets in SGPRs, the
+// lane offset in one VGPR.
+template <int NFRAG>
+__device__ __forceinline__ void stage(__amdgpu_buffer_rsrc_t rs, int first, f32x4 *dst, int wave,
+                                      int lane_bytes)
 {
+    static_assert(NFRAG % 4 == 0, "fragments are split over 4 wavefronts");
 #pragma unroll
-    for (int f = 0; f < RT; ++f) {
-        const int fr = 4 * f + wave;  // fragment of this wave
+    for (int f = 0; f < NFRAG / 4; ++f) {
+        const int fr = 4 * f + wave;
         __builtin_amdgcn_raw_ptr_buffer_load_lds(
             rs, (__attribute__((address_space(3))) void *)(dst + fr * 64), 16, lane_bytes,
-            (slab * 4 * RT + fr) * 1024, 0, 0);
+            (first + fr) * 1024, 0, 0);
     }
+}
+
+// s_waitcnt vmcnt(N) alone (gfx9 encoding: vmcnt in bits 3:0 and 15:14,
+// expcnt 6:4 and lgkmcnt 11:8 left at their no-wait maximum).  Vector memory
+// loads retire in order, so this waits for all but the N most recent.
+template <int N>
+__device__ __forceinline__ void wait_vmcnt()
+{
+    static_assert(N >= 0 && N < 64, "vmcnt is six bits");
+    __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
 }
 
 // Value of x that the compiler must treat as depending on d: used to keep
@@ -149,23 +161,47 @@ __device__ __forceinline__ uint32_t after(uint32_t x, float d)
     return x;
 }
 
-// Fused stepper.  Workgroup = 4 wavefronts = 4 tiles of 5 chains; the
-// transform tables stream through a double-buffered LDS slab shared by all
-// four tiles, so each table byte crosses L2 once per workgroup and step.
-// Table layout: [gemm (2)][slab q (RT/2)][row tile (RT)][fragment f (4)][lane]
-// with 16-byte fragments: BF16 f = (odd hi, odd lo, even hi, even lo) of one
-// K = 32 slab; FP32 f = (odd t=2q, odd t=2q+1, even t=2q, even t=2q+1), each
-// four K = 4 slices.
+// Fused stepper.  Workgroup = 4 wavefronts = 4 tiles of 5 chains.  The
+// transform tables of one step are a linear sequence of NS = 2 RT stages of
+// 2 RT fragments (1 KB each, 16 bytes per lane):
+//   stage t <  RT : u = chi R, K slab q = t/2, row tiles I of half t%2, [I][f]
+//   stage t >= RT : C * chi^T g for mode row tile J = t - RT, [q][f]
+// BF16: f = (odd hi, odd lo, even hi, even lo) of a K = 32 slab;
+// FP32: f = (odd t=2q, odd t=2q+1, even t=2q, even t=2q+1), four K = 4 slices.
+// Stages live in NB LDS buffers shared by the four tiles.  When all NS
+// stages fit (M <= 192) they are loaded once per launch; otherwise they
+// stream from L2 with a prefetch distance of NB - 1 stages: a step needs the
+// whole table (256 KB at M = 256) on every CU, and L2 latency is only covered
+// with ~100 KB in flight.  Each table byte crosses L2 once per workgroup and
+// step.  The coupling table carries C_p (Eq. f2) on its rows and its
+// accumulators start from E_p R_p + W_p eta_p (+ shear), so the product is
+// the new amplitude.
+constexpr int kLdsBytes = 150 * 1024;  // for stage buffers (of 160 KB per CU)
+constexpr int num_buffers(int RT)
+{
+    const int stages = 2 * RT, stage_bytes = 2 * RT * 1024;
+    const int fit = kLdsBytes / stage_bytes;
+    return fit >= stages ? stages : fit;
+}
+
 template <int RT, bool BF16>
 __global__ __launch_bounds__(256) void fused_kernel(FusedArgs a)
 {
     constexpr int KS = RT / 2;
-    constexpr int SLAB = 4 * RT * 64;  // f32x4 per slab
-    __shared__ float cf[4 * 32 * RT];  // E, C, W, gdt*E per mode slot
-    __shared__ f32x4 xb[2][SLAB];
+    constexpr int NSMAX = 2 * RT;    // stages per step with every coupling row
+    // coupling row tiles beyond a.jc carry only modes whose C_p is negligible
+    const int NS = RT + a.jc;        // stages per step
+    constexpr int SF = 2 * RT;       // fragments per stage
+    constexpr int HALF = RT / 2;     // row tiles per half slab
+    constexpr int NB = num_buffers(RT);
+    constexpr bool RESIDENT = NB >= NSMAX;
+    constexpr int DIST = RESIDENT ? 0 : NB - 1;  // prefetch distance
+    static_assert(RESIDENT || (DIST - 1) * (SF / 4) < 64, "vmcnt range");
+    __shared__ float cf[3 * 32 * RT];  // E, W, gdt*E per mode slot
+    __shared__ f32x4 xb[NB][SF * 64];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    for (int i = threadIdx.x; i < 4 * 32 * RT; i += blockDim.x) cf[i] = a.coef[i];
+    for (int i = threadIdx.x; i < 3 * 32 * RT; i += blockDim.x) cf[i] = a.coef[i];
 
     const int tile = blockIdx.x * 4 + wave;
     const bool has_tile = tile < a.ntiles;  // idle waves still stage and sync
@@ -189,23 +225,67 @@ __global__ __launch_bounds__(256) void fused_kernel(FusedArgs a)
     const float xlane = alpha == 0 ? 1.0f : 0.0f;  // lanes holding x components
     double r0 = com_lane ? a.R0[(size_t)tile * 16 + col] : 0.0;
 
-    int buf = 0;
+    // stage t of any step lives in buffer (b0 + t) % NB; b0 advances by NS
+    // per step (always 0 when the table is resident)
+    int b0 = 0;
     if (a.nonlinear) {
-        stage_slab<RT>(xrs, 0, xb[0], wave, lane_bytes);
-        __builtin_amdgcn_s_waitcnt(0);
+        if constexpr (RESIDENT) {
+#pragma unroll
+            for (int t = 0; t < NSMAX; ++t) stage<SF>(xrs, t * SF, xb[t], wave, lane_bytes);
+            wait_vmcnt<0>();
+        } else {
+            // the first DIST stages (wrapping into the next steps when a step
+            // has fewer stages than the prefetch distance)
+            int issued = 0;
+            for (int t = 0; t < DIST; ++t)
+                if (t / NS < a.n_steps) {
+                    stage<SF>(xrs, (t % NS) * SF, xb[t], wave, lane_bytes);
+                    ++issued;
+                }
+            if (issued == DIST)
+                wait_vmcnt<(DIST - 1) * (SF / 4)>();  // stage 0 landed (own loads)
+            else
+                wait_vmcnt<0>();
+        }
     }
     __syncthreads();
 
+    // Streaming: issue the copy of stage t + DIST (of this step or, wrapping,
+    // of the next) and, after the compute of stage t, wait until stage t + 1
+    // has landed (loads retire in order).
+    auto prefetch = [&](int t, int s) -> bool {
+        if constexpr (RESIDENT) {
+            return false;
+        } else {
+            // stage t + DIST counted from the start of this step, as (step
+            // ahead, stage of that step); nothing beyond the last step
+            const int tn = t + DIST;
+            if (s + tn / NS < a.n_steps) {
+                stage<SF>(xrs, (tn % NS) * SF, xb[(b0 + tn) % NB], wave, lane_bytes);
+                return true;
+            }
+            return false;
+        }
+    };
+    // outstanding loads of this wave after stage t: stages t+1 .. t+DIST that
+    // were issued; all but stage t+1 may stay in flight
+    auto finish = [&](int t, int s) {
+        if constexpr (!RESIDENT) {
+            // last stage issued so far, counted from the start of this step
+            const int last = min(t + DIST, (a.n_steps - s) * NS - 1);
+            const int ahead = last - (t + 1);  // issued beyond t+1
+            if (ahead >= DIST - 1)
+                wait_vmcnt<(DIST - 1) * (SF / 4)>();
+            else
+                wait_vmcnt<0>();
+        }
+        __syncthreads();
+    };
     for (int s = 0; s < a.n_steps; ++s) {
         const int64_t k = a.step0 + s;
-        f32x4 dO[RT], dE[RT];
-        if (!a.nonlinear) {
-#pragma unroll
-            for (int J = 0; J < RT; ++J) {
-                dO[J] = f32x4{0.f, 0.f, 0.f, 0.f};
-                dE[J] = f32x4{0.f, 0.f, 0.f, 0.f};
-            }
-        } else {
+        f32x4 Gp[RT], Gm[RT];
+        [[maybe_unused]] bf16x8 gph[KS], gpl[KS], gmh[KS], gml[KS];
+        if (a.nonlinear) {
             // ---- u = chi R: half-bond rows I, K over mode slabs q
             f32x4 aS[RT], aA[RT];
 #pragma unroll
@@ -213,20 +293,21 @@ __global__ __launch_bounds__(256) void fused_kernel(FusedArgs a)
                 aS[I] = f32x4{0.f, 0.f, 0.f, 0.f};
                 aA[I] = f32x4{0.f, 0.f, 0.f, 0.f};
             }
+            [[maybe_unused]] bf16x8 boh, bol, beh, bel;
 #pragma unroll
-            for (int q = 0; q < KS; ++q) {
-                // prefetch the next slab: next q of this product, else the
-                // first slab of the coupling product
-                const int nq = (q + 1 < KS) ? (q + 1) : KS;
-                stage_slab<RT>(xrs, nq, xb[buf ^ 1], wave, lane_bytes);
-                const f32x4 *xs = xb[buf];
+            for (int t = 0; t < RT; ++t) {
+                const int q = t / 2, h = t % 2;
+                prefetch(t, s);
+                const f32x4 *xs = xb[(b0 + t) % NB];
                 if constexpr (BF16) {
-                    bf16x8 boh, bol, beh, bel;
-                    split_bf16(Ro[2 * q], Ro[2 * q + 1], boh, bol);
-                    split_bf16(Re[2 * q], Re[2 * q + 1], beh, bel);
+                    if (h == 0) {
+                        split_bf16(Ro[2 * q], Ro[2 * q + 1], boh, bol);
+                        split_bf16(Re[2 * q], Re[2 * q + 1], beh, bel);
+                    }
 #pragma unroll
-                    for (int I = 0; I < RT; ++I) {
-                        const f32x4 *fr = xs + (I * 4) * 64 + lane;
+                    for (int ii = 0; ii < HALF; ++ii) {
+                        const int I = h * HALF + ii;
+                        const f32x4 *fr = xs + (ii * 4) * 64 + lane;
                         const bf16x8 xoh = __builtin_bit_cast(bf16x8, fr[0]);
                         const bf16x8 xol = __builtin_bit_cast(bf16x8, fr[64]);
                         const bf16x8 xeh = __builtin_bit_cast(bf16x8, fr[128]);
@@ -240,86 +321,43 @@ __global__ __launch_bounds__(256) void fused_kernel(FusedArgs a)
                     }
                 } else {
 #pragma unroll
-                    for (int I = 0; I < RT; ++I) {
-                        const f32x4 *fr = xs + (I * 4) * 64 + lane;
+                    for (int ii = 0; ii < HALF; ++ii) {
+                        const int I = h * HALF + ii;
+                        const f32x4 *fr = xs + (ii * 4) * 64 + lane;
 #pragma unroll
-                        for (int h = 0; h < 2; ++h) {
-                            const f32x4 xo = fr[h * 64], xe = fr[(2 + h) * 64];
+                        for (int hh = 0; hh < 2; ++hh) {
+                            const f32x4 xo = fr[hh * 64], xe = fr[(2 + hh) * 64];
 #pragma unroll
                             for (int r = 0; r < 4; ++r) {
-                                aS[I] = mfma_f32(xo[r], Ro[2 * q + h][r], aS[I]);
-                                aA[I] = mfma_f32(xe[r], Re[2 * q + h][r], aA[I]);
+                                aS[I] = mfma_f32(xo[r], Ro[2 * q + hh][r], aS[I]);
+                                aA[I] = mfma_f32(xe[r], Re[2 * q + hh][r], aA[I]);
                             }
                         }
                     }
                 }
-                __builtin_amdgcn_s_waitcnt(0);
-                __syncthreads();
-                buf ^= 1;
+                finish(t, s);
             }
-            // ---- bond forces
-            f32x4 Gp[RT], Gm[RT];
+            // ---- bond forces (and their BF16 split for the coupling product)
 #pragma unroll
-            for (int I = 0; I < RT; ++I)
-                bond_forces(aS[I], aA[I], alpha, a.lin, Gp[I], Gm[I]);
-            // ---- Delta H = chi^T g: mode rows J, K over half-bond slabs q
+            for (int I = 0; I < RT; ++I) bond_forces(aS[I], aA[I], alpha, a.lin, Gp[I], Gm[I]);
+            if constexpr (BF16) {
 #pragma unroll
-            for (int J = 0; J < RT; ++J) {
-                dO[J] = f32x4{0.f, 0.f, 0.f, 0.f};
-                dE[J] = f32x4{0.f, 0.f, 0.f, 0.f};
-            }
-#pragma unroll
-            for (int q = 0; q < KS; ++q) {
-                if (q + 1 < KS)
-                    stage_slab<RT>(xrs, KS + q + 1, xb[buf ^ 1], wave, lane_bytes);
-                else if (s + 1 < a.n_steps)
-                    stage_slab<RT>(xrs, 0, xb[buf ^ 1], wave, lane_bytes);
-                const f32x4 *xs = xb[buf];
-                if constexpr (BF16) {
-                    bf16x8 gph, gpl, gmh, gml;
-                    split_bf16(Gp[2 * q], Gp[2 * q + 1], gph, gpl);
-                    split_bf16(Gm[2 * q], Gm[2 * q + 1], gmh, gml);
-#pragma unroll
-                    for (int J = 0; J < RT; ++J) {
-                        const f32x4 *fr = xs + (J * 4) * 64 + lane;
-                        const bf16x8 xoh = __builtin_bit_cast(bf16x8, fr[0]);
-                        const bf16x8 xol = __builtin_bit_cast(bf16x8, fr[64]);
-                        const bf16x8 xeh = __builtin_bit_cast(bf16x8, fr[128]);
-                        const bf16x8 xel = __builtin_bit_cast(bf16x8, fr[192]);
-                        dO[J] = mfma_bf16(xoh, gph, dO[J]);
-                        dE[J] = mfma_bf16(xeh, gmh, dE[J]);
-                        dO[J] = mfma_bf16(xoh, gpl, dO[J]);
-                        dE[J] = mfma_bf16(xeh, gml, dE[J]);
-                        dO[J] = mfma_bf16(xol, gph, dO[J]);
-                        dE[J] = mfma_bf16(xel, gmh, dE[J]);
-                    }
-                } else {
-#pragma unroll
-                    for (int J = 0; J < RT; ++J) {
-                        const f32x4 *fr = xs + (J * 4) * 64 + lane;
-#pragma unroll
-                        for (int h = 0; h < 2; ++h) {
-                            const f32x4 xo = fr[h * 64], xe = fr[(2 + h) * 64];
-#pragma unroll
-                            for (int r = 0; r < 4; ++r) {
-                                dO[J] = mfma_f32(xo[r], Gp[2 * q + h][r], dO[J]);
-                                dE[J] = mfma_f32(xe[r], Gm[2 * q + h][r], dE[J]);
-                            }
-                        }
-                    }
+                for (int q = 0; q < KS; ++q) {
+                    split_bf16(Gp[2 * q], Gp[2 * q + 1], gph[q], gpl[q]);
+                    split_bf16(Gm[2 * q], Gm[2 * q + 1], gmh[q], gml[q]);
                 }
-                __builtin_amdgcn_s_waitcnt(0);
-                __syncthreads();
-                buf ^= 1;
             }
         }
-        // ---- mode update: lane holds p = 32J + 8g + m, m = 0..7; even p =
-        // .. + 2r in Re[J][r], odd p = .. + 2r + 1 in Ro[J][r]
+        // ---- per mode tile J: start from E R + W eta (+ shear), add the
+        // coupling C * chi^T g.  Lane holds p = 32J + 8g + m, m = 0..7: even p
+        // = .. + 2r in Re[J][r], odd p = .. + 2r + 1 in Ro[J][r].
 #pragma unroll
         for (int J = 0; J < RT; ++J) {
-            // noise of tile J only after the coupling of tile J and the
-            // update of tile J-1
-            const uint32_t ch = after(after(chain, dO[J][0]), J ? Ro[J - 1][3] : dE[J][0]);
+            const int t = RT + J;
+            const bool couple = a.nonlinear && J < a.jc;
+            if (couple) prefetch(t, s);
+            const uint32_t ch =
+                after(chain, J ? Ro[J - 1][3] : (a.nonlinear ? Gm[0][0] : Re[0][0]));
             float z[8];
             normals4_f32(noise_bits(a.seed, (uint32_t)(8 * J + 2 * g), ch, k, (uint32_t)alpha,
                                     kTagMode),
@@ -328,33 +366,23 @@ __global__ __launch_bounds__(256) void fused_kernel(FusedArgs a)
                                     (uint32_t)alpha, kTagMode),
                          z + 4);
             const int cb = (J * 4 + g) * 8;
-            f32x4 ye, yo;
+            f32x4 ao, ae;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int me = cb + 2 * r, mo = me + 1;
+                ae[r] = cf[me] * Re[J][r] + cf[32 * RT + me] * z[2 * r];
+                ao[r] = cf[mo] * Ro[J][r] + cf[32 * RT + mo] * z[2 * r + 1];
+            }
             if (a.gdt != 0.0) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     // R^y of the same chain, for the x lanes only.  The lane
                     // move runs with every lane active (a DPP read from a lane
                     // masked off by a branch returns 0), then is masked.
-                    ye[r] = xlane * dpp<kRowShl1>(Re[J][r]);
-                    yo[r] = xlane * dpp<kRowShl1>(Ro[J][r]);
+                    const int me = cb + 2 * r, mo = me + 1;
+                    ae[r] += cf[64 * RT + me] * (xlane * dpp<kRowShl1>(Re[J][r]));
+                    ao[r] += cf[64 * RT + mo] * (xlane * dpp<kRowShl1>(Ro[J][r]));
                 }
-            }
-            // Columns without a chain evolve like free chains that start at
-            // zero; product columns are independent, so they never touch the
-            // real chains, and they are not written back.
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int me = cb + 2 * r, mo = me + 1;
-                float ve = cf[me] * Re[J][r] + cf[64 * RT + me] * z[2 * r];
-                float vo = cf[mo] * Ro[J][r] + cf[64 * RT + mo] * z[2 * r + 1];
-                ve += cf[32 * RT + me] * dE[J][r];
-                vo += cf[32 * RT + mo] * dO[J][r];
-                if (a.gdt != 0.0) {
-                    ve += cf[96 * RT + me] * ye[r];
-                    vo += cf[96 * RT + mo] * yo[r];
-                }
-                Re[J][r] = ve;
-                Ro[J][r] = vo;
             }
             if (J == 0) {
                 // centre of mass (p = 0, slot m = 0 of the g = 0 lanes): free
@@ -364,7 +392,44 @@ __global__ __launch_bounds__(256) void fused_kernel(FusedArgs a)
                 if (alpha == 0) nr0 += a.gdt * r0y;
                 r0 = com_lane ? nr0 : 0.0;
             }
+            if (couple) {
+                const f32x4 *xs = xb[(b0 + t) % NB];
+                if constexpr (BF16) {
+#pragma unroll
+                    for (int q = 0; q < KS; ++q) {
+                        const f32x4 *fr = xs + (q * 4) * 64 + lane;
+                        const bf16x8 xoh = __builtin_bit_cast(bf16x8, fr[0]);
+                        const bf16x8 xol = __builtin_bit_cast(bf16x8, fr[64]);
+                        const bf16x8 xeh = __builtin_bit_cast(bf16x8, fr[128]);
+                        const bf16x8 xel = __builtin_bit_cast(bf16x8, fr[192]);
+                        ao = mfma_bf16(xoh, gph[q], ao);
+                        ae = mfma_bf16(xeh, gmh[q], ae);
+                        ao = mfma_bf16(xoh, gpl[q], ao);
+                        ae = mfma_bf16(xeh, gml[q], ae);
+                        ao = mfma_bf16(xol, gph[q], ao);
+                        ae = mfma_bf16(xel, gmh[q], ae);
+                    }
+                } else {
+#pragma unroll
+                    for (int q = 0; q < KS; ++q) {
+                        const f32x4 *fr = xs + (q * 4) * 64 + lane;
+#pragma unroll
+                        for (int hh = 0; hh < 2; ++hh) {
+                            const f32x4 xo = fr[hh * 64], xe = fr[(2 + hh) * 64];
+#pragma unroll
+                            for (int r = 0; r < 4; ++r) {
+                                ao = mfma_f32(xo[r], Gp[2 * q + hh][r], ao);
+                                ae = mfma_f32(xe[r], Gm[2 * q + hh][r], ae);
+                            }
+                        }
+                    }
+                }
+                finish(t, s);
+            }
+            Ro[J] = ao;
+            Re[J] = ae;
         }
+        if constexpr (!RESIDENT) b0 = (b0 + NS) % NB;
     }
     if (!has_tile) return;
     f32x4 *Rw = reinterpret_cast<f32x4 *>(a.R) + (size_t)tile * 2 * RT * 64;
@@ -458,15 +523,16 @@ hipError_t fused_alloc(FusedBucket &f, int M, int n, bool bf16, const std::vecto
     f.ntiles = tiles_of(n);
     const int RT = f.RT, H = M / 2, Hp = 16 * RT;
     // half-bond x half-mode tables: Xo[i][j] = chi_{i+1, 2j+1}, Xe[i][j] = chi_{i+1, 2j}
-    std::vector<double> Xo((size_t)Hp * Hp, 0.0), Xe((size_t)Hp * Hp, 0.0);
+    f.Xo.assign((size_t)Hp * Hp, 0.0);
+    f.Xe.assign((size_t)Hp * Hp, 0.0);
     auto chi = [&](int bond, int p) {
         return phi[(size_t)bond * M + p] - phi[(size_t)(bond - 1) * M + p];
     };
     for (int i = 0; i < H; ++i)
         for (int j = 0; j < H; ++j) {
-            Xo[(size_t)i * Hp + j] = chi(i + 1, 2 * j + 1);
+            f.Xo[(size_t)i * Hp + j] = chi(i + 1, 2 * j + 1);
             // the middle bond has no antisymmetric part: chi_{H, even} = 0 exactly
-            Xe[(size_t)i * Hp + j] = (j == 0 || i == H - 1) ? 0.0 : chi(i + 1, 2 * j);
+            f.Xe[(size_t)i * Hp + j] = (j == 0 || i == H - 1) ? 0.0 : chi(i + 1, 2 * j);
         }
     const size_t xb = x_bytes(RT, bf16);
     hipError_t e;
@@ -475,53 +541,68 @@ hipError_t fused_alloc(FusedBucket &f, int M, int n, bool bf16, const std::vecto
         return e;
     if ((e = hipMalloc((void **)&f.d_R0, sizeof(double) * 16 * (size_t)f.ntiles)) != hipSuccess)
         return e;
-    if ((e = hipMalloc((void **)&f.d_coef, sizeof(float) * 128 * (size_t)RT)) != hipSuccess)
+    if ((e = hipMalloc((void **)&f.d_coef, sizeof(float) * 96 * (size_t)RT)) != hipSuccess)
         return e;
-    // fragment order [gemm][slab q][row tile A][f][lane][16 bytes], see fused_kernel
-    const double *src[2] = {Xo.data(), Xe.data()};
-    const int KS = RT / 2;
-    auto at = [&](int kind, int row, int colx) { return src[kind][(size_t)row * Hp + colx]; };
-    if (!bf16) {
-        std::vector<float> h((size_t)2 * KS * RT * 4 * 64 * 4);
-        for (int gm = 0; gm < 2; ++gm)
-            for (int q = 0; q < KS; ++q)
-                for (int A = 0; A < RT; ++A)
-                    for (int fr = 0; fr < 4; ++fr)
-                        for (int l = 0; l < 64; ++l)
-                            for (int r = 0; r < 4; ++r) {
-                                const int kind = fr / 2, t = 2 * q + (fr % 2);
-                                const int lo = l % 16, kk = 16 * t + 4 * (l / 16) + r;
-                                // GEMM1: A[i = 16A + lo][k]; GEMM2: X^T, A[j = 16A + lo][k]
-                                double v = gm == 0 ? at(kind, 16 * A + lo, kk)
-                                                   : at(kind, kk, 16 * A + lo);
-                                if (gm == 1 && kk == H - 1) v *= 0.5;  // middle bond, see bond_forces
-                                h[(((((size_t)gm * KS + q) * RT + A) * 4 + fr) * 64 + l) * 4 + r] =
-                                    (float)v;
-                            }
-        e = hipMemcpy(f.d_X, h.data(), xb, hipMemcpyHostToDevice);
-    } else {
-        std::vector<__bf16> h((size_t)2 * KS * RT * 4 * 64 * 8);
-        for (int gm = 0; gm < 2; ++gm)
-            for (int q = 0; q < KS; ++q)
-                for (int A = 0; A < RT; ++A)
-                    for (int fr = 0; fr < 4; ++fr)
-                        for (int l = 0; l < 64; ++l)
-                            for (int el = 0; el < 8; ++el) {
-                                const int kind = fr / 2, part = fr % 2;  // hi, lo
-                                const int lo = l % 16, kk = kslab_index(q, l / 16, el);
-                                double v = gm == 0 ? at(kind, 16 * A + lo, kk)
-                                                   : at(kind, kk, 16 * A + lo);
-                                if (gm == 1 && kk == H - 1) v *= 0.5;  // middle bond, see bond_forces
-                                const __bf16 vh = (__bf16)(float)v;
-                                const __bf16 out =
-                                    part == 0 ? vh : (__bf16)(float)(v - (double)(float)vh);
-                                h[(((((size_t)gm * KS + q) * RT + A) * 4 + fr) * 64 + l) * 8 + el] =
-                                    out;
-                            }
-        e = hipMemcpy(f.d_X, h.data(), xb, hipMemcpyHostToDevice);
-    }
-    if (e != hipSuccess) return e;
+    if ((e = hipMemset(f.d_X, 0, xb)) != hipSuccess) return e;
     return hipMemset(f.d_R, 0, sizeof(float) * state_floats(RT, f.ntiles));
+}
+
+// Write the fragments of one product into the fragment-ordered table.
+//   gm = 0: u = chi R, fragment (q, I, f): A[i = 16I + lane%16][k], k over mode slab q
+//   gm = 1: C chi^T g, fragment (J, q, f): A[j = 16J + lane%16][k], k over bond slab q,
+//           rows scaled by C_p, the middle bond's column halved (see bond_forces)
+static hipError_t upload_table(const FusedBucket &f, int gm, int M, const double *C,
+                               hipStream_t st)
+{
+    const int RT = f.RT, KS = RT / 2, H = M / 2, Hp = 16 * RT;
+    const double *src[2] = {f.Xo.data(), f.Xe.data()};
+    auto value = [&](int kind, int A, int kk, int lo) {
+        if (gm == 0) return src[kind][(size_t)(16 * A + lo) * Hp + kk];
+        const int j = 16 * A + lo;                 // half-mode row
+        const int p = kind == 0 ? 2 * j + 1 : 2 * j;  // mode
+        double v = src[kind][(size_t)kk * Hp + j];
+        if (kk == H - 1) v *= 0.5;
+        return (p < M) ? v * C[p] : 0.0;
+    };
+    auto frag = [&](int A, int q, int fr) -> size_t {  // fragment index
+        return gm == 0 ? ((size_t)q * RT + A) * 4 + fr
+                       : (size_t)KS * RT * 4 + ((size_t)A * KS + q) * 4 + fr;
+    };
+    const size_t nfr = (size_t)KS * RT * 4;  // fragments of one product
+    hipError_t e;
+    if (!f.bf16) {
+        std::vector<float> h(nfr * 256);
+        for (int q = 0; q < KS; ++q)
+            for (int A = 0; A < RT; ++A)
+                for (int fr = 0; fr < 4; ++fr)
+                    for (int l = 0; l < 64; ++l)
+                        for (int r = 0; r < 4; ++r) {
+                            const int kind = fr / 2, t = 2 * q + (fr % 2);
+                            const int kk = 16 * t + 4 * (l / 16) + r;
+                            h[((frag(A, q, fr) - (gm ? nfr : 0)) * 64 + l) * 4 + r] =
+                                (float)value(kind, A, kk, l % 16);
+                        }
+        e = hipMemcpyAsync((char *)f.d_X + (gm ? nfr * 1024 : 0), h.data(), nfr * 1024,
+                           hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+    } else {
+        std::vector<__bf16> h(nfr * 512);
+        for (int q = 0; q < KS; ++q)
+            for (int A = 0; A < RT; ++A)
+                for (int fr = 0; fr < 4; ++fr)
+                    for (int l = 0; l < 64; ++l)
+                        for (int el = 0; el < 8; ++el) {
+                            const int kind = fr / 2, part = fr % 2;  // hi, lo
+                            const double v = value(kind, A, kslab_index(q, l / 16, el), l % 16);
+                            const __bf16 vh = (__bf16)(float)v;
+                            h[((frag(A, q, fr) - (gm ? nfr : 0)) * 64 + l) * 8 + el] =
+                                part == 0 ? vh : (__bf16)(float)(v - (double)(float)vh);
+                        }
+        e = hipMemcpyAsync((char *)f.d_X + (gm ? nfr * 1024 : 0), h.data(), nfr * 1024,
+                           hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+    }
+    return e;
 }
 
 void fused_free(FusedBucket &f)
@@ -553,22 +634,34 @@ hipError_t fused_set_coefs(FusedBucket &f, const ModeCoefs &mc, int M, double li
                            hipStream_t st)
 {
     const int RT = f.RT;
-    std::vector<float> h((size_t)128 * RT, 0.0f);
     // slot (J, g, m) <-> mode p = 32J + 8g + m; p = 0 (centre of mass) and
-    // padding p >= M stay zero
-    for (int slot = 0; slot < 32 * RT; ++slot) {
-        const int p = slot;
-        if (p == 0 || p >= M) continue;
-        h[slot] = (float)mc.E[p];
-        h[32 * RT + slot] = (float)mc.C[p];
-        h[64 * RT + slot] = (float)mc.W[p];
-        h[96 * RT + slot] = (float)(gdt * mc.E[p]);
+    // padding p >= M stay zero.  E, W, gdt*E per slot; C goes into the table.
+    std::vector<float> h((size_t)96 * RT, 0.0f);
+    for (int p = 1; p < M && p < 32 * RT; ++p) {
+        h[p] = (float)mc.E[p];
+        h[32 * RT + p] = (float)mc.W[p];
+        h[64 * RT + p] = (float)(gdt * mc.E[p]);
     }
     f.W0 = mc.W[0];
     f.gdt = gdt;
     f.lin = (float)lin;
-    hipError_t e = hipMemcpyAsync(f.d_coef, h.data(), sizeof(float) * h.size(),
-                                  hipMemcpyHostToDevice, st);
+    // Coupling rows whose kick is below FP32 resolution of the update are
+    // skipped (Eq. f4: for modes equilibrated within a step the coupling is
+    // exponentially small).  |Delta H_p| <= |chi_p| |g| <= 2 s_p * 3 sqrt(M)
+    // (column norm 2 s_p from Eq. e6; |g_n| = |1 - (1-2nu) l_n| <= 3 for
+    // bonds shorter than four rest lengths); a row tile is kept if any of
+    // its modes has C_p * 6 s_p sqrt(M) >= 2^-30 W_p.
+    const double pi = 3.141592653589793238462643383279502884;
+    int pmax = 0;
+    for (int p = 1; p < M; ++p) {
+        const double sp = std::sin(pi * p / (2.0 * M));
+        if (mc.C[p] * 6.0 * sp * std::sqrt((double)M) >= std::ldexp(mc.W[p], -30)) pmax = p;
+    }
+    f.JC = std::min(RT, pmax / 32 + 1);
+    hipError_t e;
+    if ((e = upload_table(f, 0, M, mc.C.data(), st)) != hipSuccess) return e;
+    if ((e = upload_table(f, 1, M, mc.C.data(), st)) != hipSuccess) return e;
+    e = hipMemcpyAsync(f.d_coef, h.data(), sizeof(float) * h.size(), hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return e;
     return hipStreamSynchronize(st);
 }
@@ -599,6 +692,7 @@ hipError_t fused_step(FusedBucket &f, const int32_t *ids, int M, int n, uint64_t
     a.n = n;
     a.ntiles = f.ntiles;
     a.x_bytes = (int)x_bytes(f.RT, f.bf16 != 0);
+    a.jc = f.JC;
     a.seed = seed;
     a.step0 = step0;
     a.n_steps = n_steps;
