@@ -278,7 +278,7 @@ int dm_init_chains(dm_ctx **out, int32_t n_chains, const int32_t *beads, const d
         if (e == hipSuccess)
             e = dm::launch_gemm_f64(b.d_Afwd, b.d_r, b.d_R64, b.M, 3 * b.n, ctx->stream);
         if (e == hipSuccess && fused_precision(precision)) {
-            e = dm::fused_alloc(b.fused, b.M, b.n, precision == DM_BF16X3, phi);
+            e = dm::fused_alloc(b.fused, b.M, b.n, precision == DM_BF16X3);
             if (e == hipSuccess) e = dm::fused_pack_modes(b.fused, b.d_R64, b.M, b.n, ctx->stream);
         }
         // the host staging buffers die with this scope: finish the uploads first

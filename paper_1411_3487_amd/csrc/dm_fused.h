@@ -17,16 +17,18 @@ struct FusedBucket {
     void *d_X = nullptr;     // bond-mode transform fragments (see dm_fused.hip)
     float *d_R = nullptr;    // internal mode amplitudes, fragment order
     double *d_R0 = nullptr;  // centre-of-mass mode, ntiles * 16 doubles
-    float *d_coef = nullptr; // per-mode E, W, gdt*E in lane order
+    float *d_coef = nullptr; // per-slot update coefficients (see dm_fused.hip)
+    double *d_sig = nullptr; // sigma_p of the even modes, by half-mode slot
     int JC = 0;              // coupling row tiles with non-negligible C_p
+    int resident = 0;        // tables held in LDS for the whole launch
     double W0 = 0.0, gdt = 0.0;
     float lin = 0.0f;
-    std::vector<double> Xo, Xe;  // host FP64 half tables (the coupling table
-                                 // is rebuilt with C_p whenever dtau changes)
+    std::vector<double> Xo, Se, sig;  // host FP64 half tables (the coupling
+                                      // table is rebuilt when dtau changes)
 };
 
 bool fused_supports(int M);
-hipError_t fused_alloc(FusedBucket &f, int M, int n, bool bf16, const std::vector<double> &phi);
+hipError_t fused_alloc(FusedBucket &f, int M, int n, bool bf16);
 void fused_free(FusedBucket &f);
 hipError_t fused_pack_modes(FusedBucket &f, const double *R64, int M, int n, hipStream_t st);
 hipError_t fused_unpack_modes(const FusedBucket &f, double *R64, int M, int n, hipStream_t st);

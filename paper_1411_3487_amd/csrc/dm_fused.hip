@@ -6,10 +6,11 @@
 //   g_n = u_n (1/|u_n| - (1-2nu))                          (Eqs. e4, e11)
 //   Delta H = chi^T g                                      (Eq. e11)
 //   R <- E R + C Delta H + W eta (+ shear)                 (Eqs. d3, d6, f2, btum)
-// with chi_{n,p} = phi_{n,p} - phi_{n-1,p} (Eq. e3, computed as the
-// difference).  Applying the bond difference inside the transform keeps the
-// O(|u|) bond vectors free of the O(M |u|) positions, which is what lets the
-// transforms run in FP32 or split BF16.
+// with chi_{n,p} = phi_{n,p} - phi_{n-1,p} = sigma_p sin(p n pi/M),
+// sigma_p = -2 sqrt(2/M) sin(p pi/2M) (the difference of two modes of
+// Eq. c8; Eq. e3 prints the opposite sign).  Applying the bond difference
+// inside the transform keeps the O(|u|) bond vectors free of the O(M |u|)
+// positions, which is what lets the transforms run in FP32 or split BF16.
 //
 // Mirror symmetry (Sec. 5a: phi_{N-n,p} = (-1)^p phi_{n,p}) gives
 // chi_{M-n,p} = (-1)^{p+1} chi_{n,p}: for half-bond rows i = 1..H (H = M/2)
@@ -19,6 +20,15 @@
 //   Delta H_{p even} = sum_i chi_{i,p} (g_i - g_{M-i}),
 // (the middle bond i = H counted once), so each transform is two H x H
 // products instead of one M x M product: half the MFMA work.
+//
+// Even modes.  Slot j of the even half holds p = 2j + 2 (the p = 0 centre of
+// mass is kept apart, in FP64) scaled as Rt_p = sigma_p R_p.  With bond row
+// i <-> bond i + 1 the even-mode table is then
+//   S_{ij} = sin((i+1)(j+1) pi / H),
+// which is symmetric, so the coupling product Delta H_even = sigma S G- reads
+// the very fragments of u = chi R: in LDS the tables take the u = chi R
+// product plus the odd-mode coupling rows only.  The update of a scaled
+// amplitude is Rt <- E Rt + sigma^2 C (S G-) + sigma W eta.
 //
 // MFMA layout.  Columns of every product are the 15 (chain, component)
 // pairs of the tile plus one unused column; col = 3 * chain + component.
@@ -47,6 +57,10 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int kChainsPerTile = 5;
+
+// Per-slot coefficients of the update, [kind][16 RT half-mode slots]: odd
+// mode E, W, gdt E; even mode E, sigma W, gdt E, sigma^2 C.
+enum { kEo, kWo, kGo, kEe, kWe, kGe, kCe, kKinds };
 
 struct FusedArgs {
     const void *X;
@@ -123,9 +137,9 @@ __device__ __forceinline__ void bond_forces(const f32x4 aS, const f32x4 aA, int 
     }
 }
 
-// Copy nfrag consecutive 1 KB fragments of the transform tables, starting at
-// fragment first, to LDS: the whole workgroup issues buffer loads that write
-// LDS directly (16 bytes per lane, no register staging).  All address
+// Copy fragments first .. first + NFRAG - 1 of the transform tables (1 KB
+// each) to LDS: the whole workgroup issues buffer loads that write LDS
+// directly (16 bytes per lane, no register staging).  All address
 // arithmetic is scalar: one buffer descriptor, the byte offsets in SGPRs, the
 // lane offset in one VGPR.
 template <int NFRAG>
@@ -140,6 +154,16 @@ __device__ __forceinline__ void stage(__amdgpu_buffer_rsrc_t rs, int first, f32x
             rs, (__attribute__((address_space(3))) void *)(dst + fr * 64), 16, lane_bytes,
             (first + fr) * 1024, 0, 0);
     }
+}
+
+// The same for a run-time fragment count (one-off loads at launch start).
+__device__ __forceinline__ void copy_frags(__amdgpu_buffer_rsrc_t rs, int first, f32x4 *dst, int n,
+                                           int wave, int lane_bytes)
+{
+    for (int fr = wave; fr < n; fr += 4)
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(
+            rs, (__attribute__((address_space(3))) void *)(dst + fr * 64), 16, lane_bytes,
+            (first + fr) * 1024, 0, 0);
 }
 
 // s_waitcnt vmcnt(N) alone (gfx9 encoding: vmcnt in bits 3:0 and 15:14,
@@ -161,47 +185,49 @@ __device__ __forceinline__ uint32_t after(uint32_t x, float d)
     return x;
 }
 
-// Fused stepper.  Workgroup = 4 wavefronts = 4 tiles of 5 chains.  The
-// transform tables of one step are a linear sequence of NS = 2 RT stages of
-// 2 RT fragments (1 KB each, 16 bytes per lane):
+// Fused stepper.  Workgroup = 4 wavefronts = 4 tiles of 5 chains sharing the
+// transform tables in LDS.  In HBM the tables are a linear sequence of
+// 2 RT stages of 2 RT fragments (1 KB each, 16 bytes per lane):
 //   stage t <  RT : u = chi R, K slab q = t/2, row tiles I of half t%2, [I][f]
-//   stage t >= RT : C * chi^T g for mode row tile J = t - RT, [q][f]
-// BF16: f = (odd hi, odd lo, even hi, even lo) of a K = 32 slab;
-// FP32: f = (odd t=2q, odd t=2q+1, even t=2q, even t=2q+1), four K = 4 slices.
-// Stages live in NB LDS buffers shared by the four tiles.  When all NS
-// stages fit (M <= 192) they are loaded once per launch; otherwise they
-// stream from L2 with a prefetch distance of NB - 1 stages: a step needs the
-// whole table (256 KB at M = 256) on every CU, and L2 latency is only covered
-// with ~100 KB in flight.  Each table byte crosses L2 once per workgroup and
-// step.  The coupling table carries C_p (Eq. f2) on its rows and its
-// accumulators start from E_p R_p + W_p eta_p (+ shear), so the product is
-// the new amplitude.
-constexpr int kLdsBytes = 150 * 1024;  // for stage buffers (of 160 KB per CU)
-constexpr int num_buffers(int RT)
-{
-    const int stages = 2 * RT, stage_bytes = 2 * RT * 1024;
-    const int fit = kLdsBytes / stage_bytes;
-    return fit >= stages ? stages : fit;
-}
+//                   BF16 f = (odd hi, odd lo, even hi, even lo) of a K = 32
+//                   slab; FP32 f = (odd t=2q, odd 2q+1, even 2q, even 2q+1),
+//                   four K = 4 slices each
+//   stage RT + J  : coupling rows of mode row tile J, [parity][q][hi, lo]
+//                   (FP32: [parity][q][K slice 2q, 2q+1]); the odd rows carry
+//                   C_p (Eq. f2) and the middle bond's column halved, the
+//                   even rows are S itself.
+// Only the first a.jc coupling row tiles are used: beyond them C_p is below
+// FP32 resolution of the update (Eq. f4).  RESIDENT: the u = chi R stages and
+// the odd coupling rows of tiles J < a.jc are loaded into LDS once per launch
+// and the even coupling rows are read from the u = chi R fragments (S is
+// symmetric).  Otherwise the RT + a.jc stages of a step stream from L2
+// through NB stage buffers with a prefetch distance of NB - 1 stages (L2
+// latency is only covered with ~100 KB in flight), and each table byte
+// crosses L2 once per workgroup and step.  The odd accumulators start from
+// E_p R_p + W_p eta_p (+ shear), so their coupling product is the new
+// amplitude; the even ones add sigma^2 C times their product.
+constexpr int kTableFrags = 152;  // LDS for transform tables, in 1 KB fragments
 
-template <int RT, bool BF16>
+template <int RT, bool BF16, bool RESIDENT>
 __global__ __launch_bounds__(256) void fused_kernel(FusedArgs a)
 {
     constexpr int KS = RT / 2;
-    constexpr int NSMAX = 2 * RT;    // stages per step with every coupling row
-    // coupling row tiles beyond a.jc carry only modes whose C_p is negligible
-    const int NS = RT + a.jc;        // stages per step
-    constexpr int SF = 2 * RT;       // fragments per stage
-    constexpr int HALF = RT / 2;     // row tiles per half slab
-    constexpr int NB = num_buffers(RT);
-    constexpr bool RESIDENT = NB >= NSMAX;
-    constexpr int DIST = RESIDENT ? 0 : NB - 1;  // prefetch distance
-    static_assert(RESIDENT || (DIST - 1) * (SF / 4) < 64, "vmcnt range");
-    __shared__ float cf[3 * 32 * RT];  // E, W, gdt*E per mode slot
-    __shared__ f32x4 xb[NB][SF * 64];
+    constexpr int SF = 2 * RT;    // fragments per stage
+    constexpr int HALF = RT / 2;  // row tiles per half slab
+    constexpr int G1 = RT * SF;   // fragments of u = chi R
+    constexpr int NB = kTableFrags / SF;
+    constexpr int DIST = RESIDENT ? 0 : NB - 1;  // prefetch distance when streaming
+    static_assert(!RESIDENT || G1 + RT <= kTableFrags, "resident tables exceed LDS");
+    static_assert(RESIDENT || (NB >= 3 && (DIST - 1) * (SF / 4) < 64), "stream buffers");
+    const int NS = RT + a.jc;  // stages per step when streaming
+    __shared__ f32x4 cf[kKinds * RT * 4];  // [kind][J][g], four slots r each
+    __shared__ f32x4 xb[kTableFrags * 64];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    for (int i = threadIdx.x; i < 3 * 32 * RT; i += blockDim.x) cf[i] = a.coef[i];
+    {
+        const f32x4 *c4 = reinterpret_cast<const f32x4 *>(a.coef);
+        for (int i = threadIdx.x; i < kKinds * RT * 4; i += blockDim.x) cf[i] = c4[i];
+    }
 
     const int tile = blockIdx.x * 4 + wave;
     const bool has_tile = tile < a.ntiles;  // idle waves still stage and sync
@@ -225,13 +251,14 @@ __global__ __launch_bounds__(256) void fused_kernel(FusedArgs a)
     const float xlane = alpha == 0 ? 1.0f : 0.0f;  // lanes holding x components
     double r0 = com_lane ? a.R0[(size_t)tile * 16 + col] : 0.0;
 
-    // stage t of any step lives in buffer (b0 + t) % NB; b0 advances by NS
-    // per step (always 0 when the table is resident)
+    // streaming: stage t of any step lives in buffer (b0 + t) % NB; b0
+    // advances by NS per step
     int b0 = 0;
     if (a.nonlinear) {
         if constexpr (RESIDENT) {
-#pragma unroll
-            for (int t = 0; t < NSMAX; ++t) stage<SF>(xrs, t * SF, xb[t], wave, lane_bytes);
+            copy_frags(xrs, 0, xb, G1, wave, lane_bytes);
+            for (int J = 0; J < a.jc; ++J)  // odd halves of the coupling stages
+                copy_frags(xrs, G1 + J * SF, xb + (G1 + J * RT) * 64, RT, wave, lane_bytes);
             wait_vmcnt<0>();
         } else {
             // the first DIST stages (wrapping into the next steps when a step
@@ -239,7 +266,7 @@ __global__ __launch_bounds__(256) void fused_kernel(FusedArgs a)
             int issued = 0;
             for (int t = 0; t < DIST; ++t)
                 if (t / NS < a.n_steps) {
-                    stage<SF>(xrs, (t % NS) * SF, xb[t], wave, lane_bytes);
+                    stage<SF>(xrs, (t % NS) * SF, xb + (t % NB) * SF * 64, wave, lane_bytes);
                     ++issued;
                 }
             if (issued == DIST)
@@ -253,18 +280,13 @@ __global__ __launch_bounds__(256) void fused_kernel(FusedArgs a)
     // Streaming: issue the copy of stage t + DIST (of this step or, wrapping,
     // of the next) and, after the compute of stage t, wait until stage t + 1
     // has landed (loads retire in order).
-    auto prefetch = [&](int t, int s) -> bool {
-        if constexpr (RESIDENT) {
-            return false;
-        } else {
+    auto prefetch = [&](int t, int s) {
+        if constexpr (!RESIDENT) {
             // stage t + DIST counted from the start of this step, as (step
             // ahead, stage of that step); nothing beyond the last step
             const int tn = t + DIST;
-            if (s + tn / NS < a.n_steps) {
-                stage<SF>(xrs, (tn % NS) * SF, xb[(b0 + tn) % NB], wave, lane_bytes);
-                return true;
-            }
-            return false;
+            if (s + tn / NS < a.n_steps)
+                stage<SF>(xrs, (tn % NS) * SF, xb + ((b0 + tn) % NB) * SF * 64, wave, lane_bytes);
         }
     };
     // outstanding loads of this wave after stage t: stages t+1 .. t+DIST that
@@ -278,8 +300,14 @@ __global__ __launch_bounds__(256) void fused_kernel(FusedArgs a)
                 wait_vmcnt<(DIST - 1) * (SF / 4)>();
             else
                 wait_vmcnt<0>();
+            __syncthreads();
         }
-        __syncthreads();
+    };
+    auto stage_at = [&](int t) -> const f32x4 * {
+        if constexpr (RESIDENT)
+            return xb + t * SF * 64;
+        else
+            return xb + ((b0 + t) % NB) * SF * 64;
     };
     for (int s = 0; s < a.n_steps; ++s) {
         const int64_t k = a.step0 + s;
@@ -298,7 +326,7 @@ __global__ __launch_bounds__(256) void fused_kernel(FusedArgs a)
             for (int t = 0; t < RT; ++t) {
                 const int q = t / 2, h = t % 2;
                 prefetch(t, s);
-                const f32x4 *xs = xb[(b0 + t) % NB];
+                const f32x4 *xs = stage_at(t);
                 if constexpr (BF16) {
                     if (h == 0) {
                         split_bf16(Ro[2 * q], Ro[2 * q + 1], boh, bol);
@@ -348,9 +376,13 @@ __global__ __launch_bounds__(256) void fused_kernel(FusedArgs a)
                 }
             }
         }
-        // ---- per mode tile J: start from E R + W eta (+ shear), add the
-        // coupling C * chi^T g.  Lane holds p = 32J + 8g + m, m = 0..7: even p
-        // = .. + 2r in Re[J][r], odd p = .. + 2r + 1 in Ro[J][r].
+        // ---- per mode tile J: E R + W eta (+ shear) and the coupling.  Lane
+        // holds half-mode slots j = 16J + 4g + r: odd p = 2j + 1 in Ro[J][r],
+        // even p = 2j + 2 (scaled) in Re[J][r].  Normal p of the step is
+        // element p % 4 of Philox block p / 4, so a lane group draws normals
+        // 32J + 8g .. + 7 and takes normal 32J + 8g + 8 (its even slot r = 3)
+        // from the next lane group; lane group 3 gets it one tile later.
+        float wcarry = 0.0f;  // W of the even slot r = 3 of the previous tile
 #pragma unroll
         for (int J = 0; J < RT; ++J) {
             const int t = RT + J;
@@ -365,27 +397,31 @@ __global__ __launch_bounds__(256) void fused_kernel(FusedArgs a)
             normals4_f32(noise_bits(a.seed, (uint32_t)(8 * J + 2 * g + 1), ch, k,
                                     (uint32_t)alpha, kTagMode),
                          z + 4);
-            const int cb = (J * 4 + g) * 8;
+            const float zn = __shfl(z[0], (lane + 16) & 63, 64);
+            if (J > 0) Re[J - 1][3] += (g == 3) ? wcarry * zn : 0.0f;
+            const f32x4 Eo = cf[(kEo * RT + J) * 4 + g], Wo = cf[(kWo * RT + J) * 4 + g];
+            const f32x4 Ee = cf[(kEe * RT + J) * 4 + g], We = cf[(kWe * RT + J) * 4 + g];
             f32x4 ao, ae;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int me = cb + 2 * r, mo = me + 1;
-                ae[r] = cf[me] * Re[J][r] + cf[32 * RT + me] * z[2 * r];
-                ao[r] = cf[mo] * Ro[J][r] + cf[32 * RT + mo] * z[2 * r + 1];
+                const float ze = r < 3 ? z[2 * r + 2] : (g < 3 ? zn : 0.0f);
+                ao[r] = Eo[r] * Ro[J][r] + Wo[r] * z[2 * r + 1];
+                ae[r] = Ee[r] * Re[J][r] + We[r] * ze;
             }
+            wcarry = We[3];
             if (a.gdt != 0.0) {
+                const f32x4 Go = cf[(kGo * RT + J) * 4 + g], Ge = cf[(kGe * RT + J) * 4 + g];
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     // R^y of the same chain, for the x lanes only.  The lane
                     // move runs with every lane active (a DPP read from a lane
                     // masked off by a branch returns 0), then is masked.
-                    const int me = cb + 2 * r, mo = me + 1;
-                    ae[r] += cf[64 * RT + me] * (xlane * dpp<kRowShl1>(Re[J][r]));
-                    ao[r] += cf[64 * RT + mo] * (xlane * dpp<kRowShl1>(Ro[J][r]));
+                    ao[r] += Go[r] * (xlane * dpp<kRowShl1>(Ro[J][r]));
+                    ae[r] += Ge[r] * (xlane * dpp<kRowShl1>(Re[J][r]));
                 }
             }
             if (J == 0) {
-                // centre of mass (p = 0, slot m = 0 of the g = 0 lanes): free
+                // centre of mass (p = 0, normal 0 of the g = 0 lanes): free
                 // random walk in FP64, shear drift from R_0^y
                 const double r0y = __shfl(r0, (lane + 1) & 63, 64);
                 double nr0 = r0 + a.W0 * (double)z[0];
@@ -393,37 +429,49 @@ __global__ __launch_bounds__(256) void fused_kernel(FusedArgs a)
                 r0 = com_lane ? nr0 : 0.0;
             }
             if (couple) {
-                const f32x4 *xs = xb[(b0 + t) % NB];
+                // odd rows at xo2 + 2q (+1 for lo / the second K slice); even
+                // rows at xe2 + ES q (+1)
+                const f32x4 *xo2, *xe2;
+                constexpr int ES = RESIDENT ? 2 * SF : 2;
+                if constexpr (RESIDENT) {
+                    xo2 = xb + (G1 + J * RT) * 64 + lane;
+                    xe2 = xb + ((J / HALF) * SF + (J % HALF) * 4 + 2) * 64 + lane;
+                } else {
+                    xo2 = stage_at(t) + lane;
+                    xe2 = xo2 + RT * 64;
+                }
+                f32x4 ce = f32x4{0.f, 0.f, 0.f, 0.f};
                 if constexpr (BF16) {
 #pragma unroll
                     for (int q = 0; q < KS; ++q) {
-                        const f32x4 *fr = xs + (q * 4) * 64 + lane;
-                        const bf16x8 xoh = __builtin_bit_cast(bf16x8, fr[0]);
-                        const bf16x8 xol = __builtin_bit_cast(bf16x8, fr[64]);
-                        const bf16x8 xeh = __builtin_bit_cast(bf16x8, fr[128]);
-                        const bf16x8 xel = __builtin_bit_cast(bf16x8, fr[192]);
+                        const bf16x8 xoh = __builtin_bit_cast(bf16x8, xo2[(2 * q) * 64]);
+                        const bf16x8 xol = __builtin_bit_cast(bf16x8, xo2[(2 * q + 1) * 64]);
+                        const bf16x8 xeh = __builtin_bit_cast(bf16x8, xe2[(ES * q) * 64]);
+                        const bf16x8 xel = __builtin_bit_cast(bf16x8, xe2[(ES * q + 1) * 64]);
                         ao = mfma_bf16(xoh, gph[q], ao);
-                        ae = mfma_bf16(xeh, gmh[q], ae);
+                        ce = mfma_bf16(xeh, gmh[q], ce);
                         ao = mfma_bf16(xoh, gpl[q], ao);
-                        ae = mfma_bf16(xeh, gml[q], ae);
+                        ce = mfma_bf16(xeh, gml[q], ce);
                         ao = mfma_bf16(xol, gph[q], ao);
-                        ae = mfma_bf16(xel, gmh[q], ae);
+                        ce = mfma_bf16(xel, gmh[q], ce);
                     }
                 } else {
 #pragma unroll
                     for (int q = 0; q < KS; ++q) {
-                        const f32x4 *fr = xs + (q * 4) * 64 + lane;
 #pragma unroll
                         for (int hh = 0; hh < 2; ++hh) {
-                            const f32x4 xo = fr[hh * 64], xe = fr[(2 + hh) * 64];
+                            const f32x4 xo = xo2[(2 * q + hh) * 64], xe = xe2[(ES * q + hh) * 64];
 #pragma unroll
                             for (int r = 0; r < 4; ++r) {
                                 ao = mfma_f32(xo[r], Gp[2 * q + hh][r], ao);
-                                ae = mfma_f32(xe[r], Gm[2 * q + hh][r], ae);
+                                ce = mfma_f32(xe[r], Gm[2 * q + hh][r], ce);
                             }
                         }
                     }
                 }
+                const f32x4 Ce = cf[(kCe * RT + J) * 4 + g];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) ae[r] += Ce[r] * ce[r];
                 finish(t, s);
             }
             Ro[J] = ao;
@@ -441,19 +489,22 @@ __global__ __launch_bounds__(256) void fused_kernel(FusedArgs a)
     if (com_lane) a.R0[(size_t)tile * 16 + col] = r0;
 }
 
-// Slot of mode p >= 1 of (local chain j, component alpha) in the state.
+// Slot of mode p >= 1 of (local chain j, component alpha) in the state:
+// odd p at half-mode slot (p - 1)/2, even p at p/2 - 1.
 __device__ __forceinline__ size_t state_slot(int j, int alpha, int p, int RT)
 {
     const int T = j / kChainsPerTile, cl = j % kChainsPerTile, col = 3 * cl + alpha;
     const int set = (p & 1) ? 0 : 1;
-    const int jj = (p & 1) ? (p - 1) / 2 : p / 2;
+    const int jj = (p & 1) ? (p - 1) / 2 : p / 2 - 1;
     const int t = jj / 16, rho = jj % 16;
     const int lane = 16 * (rho / 4) + col;
     return (((size_t)T * 2 + set) * RT + t) * 256 + (size_t)lane * 4 + (rho % 4);
 }
 
-__global__ void pack_kernel(const double *__restrict__ R64, float *__restrict__ R,
-                            double *__restrict__ R0, int M, int n, int RT)
+// FP64 amplitudes [chain][component][p] -> fused state (even modes scaled
+// by sigma_p, sig[p/2 - 1]) and back.
+__global__ void pack_kernel(const double *__restrict__ R64, const double *__restrict__ sig,
+                            float *__restrict__ R, double *__restrict__ R0, int M, int n, int RT)
 {
     const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (size_t)n * 3 * M) return;
@@ -461,24 +512,27 @@ __global__ void pack_kernel(const double *__restrict__ R64, float *__restrict__ 
     const int alpha = (int)((idx / M) % 3);
     const int j = (int)(idx / ((size_t)3 * M));
     const double v = R64[idx];
-    if (p == 0) {
+    if (p == 0)
         R0[(size_t)(j / kChainsPerTile) * 16 + 3 * (j % kChainsPerTile) + alpha] = v;
-    } else {
-        R[state_slot(j, alpha, p, RT)] = (float)v;
-    }
+    else
+        R[state_slot(j, alpha, p, RT)] = (float)((p & 1) ? v : v * sig[p / 2 - 1]);
 }
 
 __global__ void unpack_kernel(const float *__restrict__ R, const double *__restrict__ R0,
-                              double *__restrict__ R64, int M, int n, int RT)
+                              const double *__restrict__ sig, double *__restrict__ R64, int M,
+                              int n, int RT)
 {
     const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (size_t)n * 3 * M) return;
     const int p = (int)(idx % M);
     const int alpha = (int)((idx / M) % 3);
     const int j = (int)(idx / ((size_t)3 * M));
-    R64[idx] = (p == 0)
-                   ? R0[(size_t)(j / kChainsPerTile) * 16 + 3 * (j % kChainsPerTile) + alpha]
-                   : (double)R[state_slot(j, alpha, p, RT)];
+    if (p == 0) {
+        R64[idx] = R0[(size_t)(j / kChainsPerTile) * 16 + 3 * (j % kChainsPerTile) + alpha];
+    } else {
+        const double v = (double)R[state_slot(j, alpha, p, RT)];
+        R64[idx] = (p & 1) ? v : v / sig[p / 2 - 1];
+    }
 }
 
 template <typename T>
@@ -498,11 +552,10 @@ int rt_of(int M)
     return ((H + 31) / 32) * 2;
 }
 size_t state_floats(int RT, int ntiles) { return (size_t)ntiles * 2 * RT * 256; }
-size_t x_bytes(int RT, bool bf16)
-{
-    // 4 products (GEMM1 odd/even, GEMM2 odd/even) of RT x RT tiles of 256 values
-    return (size_t)4 * RT * RT * 256 * (bf16 ? 2 * sizeof(__bf16) : sizeof(float));
-}
+int table_frags(int RT) { return 4 * RT * RT; }  // both products, all coupling rows
+size_t x_bytes(int RT) { return (size_t)table_frags(RT) * 1024; }
+// LDS fragments of the resident tables with jc coupling row tiles
+bool fits_resident(int RT, int jc) { return 2 * RT * RT + jc * RT <= kTableFrags; }
 
 // K index of slot e in lane group gq of K-slab q (BF16, K = 32 per slab).
 inline int kslab_index(int q, int gq, int e)
@@ -512,96 +565,119 @@ inline int kslab_index(int q, int gq, int e)
 
 unsigned nblocks(size_t n, unsigned t) { return (unsigned)((n + t - 1) / t); }
 
+const double kPi = 3.141592653589793238462643383279502884;
+
+// sin(pi m / d) for integers m, d > 0, with exact zeros at multiples of d.
+double sin_pi_frac(long m, long d)
+{
+    m %= 2 * d;
+    if (m == 0 || m == d) return 0.0;
+    return std::sin(kPi * (double)m / (double)d);
+}
+
 }  // namespace
 
 bool fused_supports(int M) { return M >= 2 && M <= 512 && (M % 2) == 0; }
 
-hipError_t fused_alloc(FusedBucket &f, int M, int n, bool bf16, const std::vector<double> &phi)
+hipError_t fused_alloc(FusedBucket &f, int M, int n, bool bf16)
 {
     f.bf16 = bf16 ? 1 : 0;
     f.RT = rt_of(M);
     f.ntiles = tiles_of(n);
     const int RT = f.RT, H = M / 2, Hp = 16 * RT;
-    // half-bond x half-mode tables: Xo[i][j] = chi_{i+1, 2j+1}, Xe[i][j] = chi_{i+1, 2j}
+    // half-bond x half-mode tables, bond row i <-> bond i + 1:
+    //   Xo[i][j] = chi_{i+1, 2j+1} = sigma_{2j+1} sin((i+1)(2j+1) pi/M)
+    //   Se[i][j] = sin((i+1)(j+1) pi/H) for i, j < H - 1 (the even modes
+    //              p = 2j + 2 < M, the bonds off the middle one), else 0
     f.Xo.assign((size_t)Hp * Hp, 0.0);
-    f.Xe.assign((size_t)Hp * Hp, 0.0);
-    auto chi = [&](int bond, int p) {
-        return phi[(size_t)bond * M + p] - phi[(size_t)(bond - 1) * M + p];
-    };
+    f.Se.assign((size_t)Hp * Hp, 0.0);
+    std::vector<double> sig((size_t)Hp, 0.0);  // sigma_{2j+2}
+    auto sigma = [&](int p) { return -2.0 * std::sqrt(2.0 / M) * sin_pi_frac(p, 2L * M); };
+    for (int j = 0; j + 1 < H; ++j) sig[j] = sigma(2 * j + 2);
     for (int i = 0; i < H; ++i)
         for (int j = 0; j < H; ++j) {
-            f.Xo[(size_t)i * Hp + j] = chi(i + 1, 2 * j + 1);
-            // the middle bond has no antisymmetric part: chi_{H, even} = 0 exactly
-            f.Xe[(size_t)i * Hp + j] = (j == 0 || i == H - 1) ? 0.0 : chi(i + 1, 2 * j);
+            f.Xo[(size_t)i * Hp + j] = sigma(2 * j + 1) * sin_pi_frac((long)(i + 1) * (2 * j + 1), M);
+            if (i + 1 < H && j + 1 < H)
+                f.Se[(size_t)i * Hp + j] = sin_pi_frac((long)(i + 1) * (j + 1), H);
         }
-    const size_t xb = x_bytes(RT, bf16);
+    f.sig = sig;
+    const size_t xb = x_bytes(RT);
     hipError_t e;
     if ((e = hipMalloc(&f.d_X, xb)) != hipSuccess) return e;
     if ((e = hipMalloc((void **)&f.d_R, sizeof(float) * state_floats(RT, f.ntiles))) != hipSuccess)
         return e;
     if ((e = hipMalloc((void **)&f.d_R0, sizeof(double) * 16 * (size_t)f.ntiles)) != hipSuccess)
         return e;
-    if ((e = hipMalloc((void **)&f.d_coef, sizeof(float) * 96 * (size_t)RT)) != hipSuccess)
+    if ((e = hipMalloc((void **)&f.d_coef, sizeof(float) * kKinds * 16 * (size_t)RT)) !=
+        hipSuccess)
+        return e;
+    if ((e = hipMalloc((void **)&f.d_sig, sizeof(double) * Hp)) != hipSuccess) return e;
+    if ((e = hipMemcpy(f.d_sig, sig.data(), sizeof(double) * Hp, hipMemcpyHostToDevice)) !=
+        hipSuccess)
         return e;
     if ((e = hipMemset(f.d_X, 0, xb)) != hipSuccess) return e;
     return hipMemset(f.d_R, 0, sizeof(float) * state_floats(RT, f.ntiles));
 }
 
-// Write the fragments of one product into the fragment-ordered table.
-//   gm = 0: u = chi R, fragment (q, I, f): A[i = 16I + lane%16][k], k over mode slab q
-//   gm = 1: C chi^T g, fragment (J, q, f): A[j = 16J + lane%16][k], k over bond slab q,
-//           rows scaled by C_p, the middle bond's column halved (see bond_forces)
-static hipError_t upload_table(const FusedBucket &f, int gm, int M, const double *C,
-                               hipStream_t st)
+// Write both products' fragments (layout at fused_kernel) for step
+// coefficients C and upload them.
+static hipError_t upload_tables(const FusedBucket &f, int M, const double *C, hipStream_t st)
 {
-    const int RT = f.RT, KS = RT / 2, H = M / 2, Hp = 16 * RT;
-    const double *src[2] = {f.Xo.data(), f.Xe.data()};
-    auto value = [&](int kind, int A, int kk, int lo) {
-        if (gm == 0) return src[kind][(size_t)(16 * A + lo) * Hp + kk];
-        const int j = 16 * A + lo;                 // half-mode row
-        const int p = kind == 0 ? 2 * j + 1 : 2 * j;  // mode
-        double v = src[kind][(size_t)kk * Hp + j];
-        if (kk == H - 1) v *= 0.5;
-        return (p < M) ? v * C[p] : 0.0;
+    const int RT = f.RT, KS = RT / 2, H = M / 2, Hp = 16 * RT, G1 = 2 * RT * RT;
+    // u = chi R: row i, K index kk (mode slot), kind 0 odd / 1 even
+    auto v1 = [&](int kind, int i, int kk) {
+        return (kind == 0 ? f.Xo : f.Se)[(size_t)i * Hp + kk];
     };
-    auto frag = [&](int A, int q, int fr) -> size_t {  // fragment index
-        return gm == 0 ? ((size_t)q * RT + A) * 4 + fr
-                       : (size_t)KS * RT * 4 + ((size_t)A * KS + q) * 4 + fr;
+    // coupling: row j (mode slot), K index kk (bond row)
+    auto v2 = [&](int kind, int j, int kk) {
+        if (kind == 1) return f.Se[(size_t)kk * Hp + j];
+        const int p = 2 * j + 1;
+        if (p >= M) return 0.0;
+        double v = f.Xo[(size_t)kk * Hp + j] * C[p];
+        if (kk == H - 1) v *= 0.5;  // the middle bond enters G+ twice
+        return v;
     };
-    const size_t nfr = (size_t)KS * RT * 4;  // fragments of one product
-    hipError_t e;
-    if (!f.bf16) {
-        std::vector<float> h(nfr * 256);
-        for (int q = 0; q < KS; ++q)
-            for (int A = 0; A < RT; ++A)
-                for (int fr = 0; fr < 4; ++fr)
-                    for (int l = 0; l < 64; ++l)
-                        for (int r = 0; r < 4; ++r) {
-                            const int kind = fr / 2, t = 2 * q + (fr % 2);
-                            const int kk = 16 * t + 4 * (l / 16) + r;
-                            h[((frag(A, q, fr) - (gm ? nfr : 0)) * 64 + l) * 4 + r] =
-                                (float)value(kind, A, kk, l % 16);
-                        }
-        e = hipMemcpyAsync((char *)f.d_X + (gm ? nfr * 1024 : 0), h.data(), nfr * 1024,
-                           hipMemcpyHostToDevice, st);
-        if (e == hipSuccess) e = hipStreamSynchronize(st);
-    } else {
-        std::vector<__bf16> h(nfr * 512);
-        for (int q = 0; q < KS; ++q)
-            for (int A = 0; A < RT; ++A)
-                for (int fr = 0; fr < 4; ++fr)
-                    for (int l = 0; l < 64; ++l)
-                        for (int el = 0; el < 8; ++el) {
-                            const int kind = fr / 2, part = fr % 2;  // hi, lo
-                            const double v = value(kind, A, kslab_index(q, l / 16, el), l % 16);
-                            const __bf16 vh = (__bf16)(float)v;
-                            h[((frag(A, q, fr) - (gm ? nfr : 0)) * 64 + l) * 8 + el] =
-                                part == 0 ? vh : (__bf16)(float)(v - (double)(float)vh);
-                        }
-        e = hipMemcpyAsync((char *)f.d_X + (gm ? nfr * 1024 : 0), h.data(), nfr * 1024,
-                           hipMemcpyHostToDevice, st);
-        if (e == hipSuccess) e = hipStreamSynchronize(st);
+    const size_t nfr = (size_t)table_frags(RT);
+    std::vector<unsigned char> h(nfr * 1024);
+    for (size_t F = 0; F < nfr; ++F) {
+        // decode fragment F
+        int prod, kind, A, q, sub;  // sub: hi/lo (BF16) or K slice (FP32)
+        if ((int)F < G1) {
+            prod = 0;
+            const int fr = (int)F % 4;
+            A = ((int)F / 4) % RT;
+            q = (int)F / 4 / RT;
+            kind = fr / 2;
+            sub = fr % 2;
+        } else {
+            prod = 1;
+            const int G = (int)F - G1;
+            sub = G % 2;
+            q = (G / 2) % KS;
+            kind = (G / 2 / KS) % 2;
+            A = G / 2 / KS / 2;
+        }
+        for (int l = 0; l < 64; ++l) {
+            const int row = 16 * A + l % 16;
+            if (f.bf16) {
+                __bf16 *o = reinterpret_cast<__bf16 *>(h.data() + F * 1024) + l * 8;
+                for (int el = 0; el < 8; ++el) {
+                    const int kk = kslab_index(q, l / 16, el);
+                    const double v = prod == 0 ? v1(kind, row, kk) : v2(kind, row, kk);
+                    const __bf16 vh = (__bf16)(float)v;
+                    o[el] = sub == 0 ? vh : (__bf16)(float)(v - (double)(float)vh);
+                }
+            } else {
+                float *o = reinterpret_cast<float *>(h.data() + F * 1024) + l * 4;
+                for (int r = 0; r < 4; ++r) {
+                    const int kk = 16 * (2 * q + sub) + 4 * (l / 16) + r;
+                    o[r] = (float)(prod == 0 ? v1(kind, row, kk) : v2(kind, row, kk));
+                }
+            }
+        }
     }
+    hipError_t e = hipMemcpyAsync(f.d_X, h.data(), h.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
     return e;
 }
 
@@ -611,14 +687,15 @@ void fused_free(FusedBucket &f)
     if (f.d_R) (void)hipFree(f.d_R);
     if (f.d_R0) (void)hipFree(f.d_R0);
     if (f.d_coef) (void)hipFree(f.d_coef);
+    if (f.d_sig) (void)hipFree(f.d_sig);
     f = FusedBucket();
 }
 
 hipError_t fused_pack_modes(FusedBucket &f, const double *R64, int M, int n, hipStream_t st)
 {
     const size_t N = (size_t)n * 3 * M;
-    hipLaunchKernelGGL(pack_kernel, dim3(nblocks(N, 256)), dim3(256), 0, st, R64, f.d_R, f.d_R0,
-                       M, n, f.RT);
+    hipLaunchKernelGGL(pack_kernel, dim3(nblocks(N, 256)), dim3(256), 0, st, R64, f.d_sig, f.d_R,
+                       f.d_R0, M, n, f.RT);
     return hipGetLastError();
 }
 
@@ -626,21 +703,31 @@ hipError_t fused_unpack_modes(const FusedBucket &f, double *R64, int M, int n, h
 {
     const size_t N = (size_t)n * 3 * M;
     hipLaunchKernelGGL(unpack_kernel, dim3(nblocks(N, 256)), dim3(256), 0, st, f.d_R, f.d_R0,
-                       R64, M, n, f.RT);
+                       f.d_sig, R64, M, n, f.RT);
     return hipGetLastError();
 }
 
 hipError_t fused_set_coefs(FusedBucket &f, const ModeCoefs &mc, int M, double lin, double gdt,
                            hipStream_t st)
 {
-    const int RT = f.RT;
-    // slot (J, g, m) <-> mode p = 32J + 8g + m; p = 0 (centre of mass) and
-    // padding p >= M stay zero.  E, W, gdt*E per slot; C goes into the table.
-    std::vector<float> h((size_t)96 * RT, 0.0f);
-    for (int p = 1; p < M && p < 32 * RT; ++p) {
-        h[p] = (float)mc.E[p];
-        h[32 * RT + p] = (float)mc.W[p];
-        h[64 * RT + p] = (float)(gdt * mc.E[p]);
+    const int RT = f.RT, Hp = 16 * RT;
+    // [kind][slot j]: odd p = 2j + 1, even p = 2j + 2 (scaled by sigma_p);
+    // padding p >= M stays zero.  C of the odd modes goes into the table.
+    std::vector<float> h((size_t)kKinds * Hp, 0.0f);
+    for (int j = 0; j < Hp; ++j) {
+        const int po = 2 * j + 1, pe = 2 * j + 2;
+        if (po < M) {
+            h[kEo * Hp + j] = (float)mc.E[po];
+            h[kWo * Hp + j] = (float)mc.W[po];
+            h[kGo * Hp + j] = (float)(gdt * mc.E[po]);
+        }
+        if (pe < M) {
+            const double sg = f.sig[j];
+            h[kEe * Hp + j] = (float)mc.E[pe];
+            h[kWe * Hp + j] = (float)(sg * mc.W[pe]);
+            h[kGe * Hp + j] = (float)(gdt * mc.E[pe]);
+            h[kCe * Hp + j] = (float)(sg * sg * mc.C[pe]);
+        }
     }
     f.W0 = mc.W[0];
     f.gdt = gdt;
@@ -649,31 +736,31 @@ hipError_t fused_set_coefs(FusedBucket &f, const ModeCoefs &mc, int M, double li
     // skipped (Eq. f4: for modes equilibrated within a step the coupling is
     // exponentially small).  |Delta H_p| <= |chi_p| |g| <= 2 s_p * 3 sqrt(M)
     // (column norm 2 s_p from Eq. e6; |g_n| = |1 - (1-2nu) l_n| <= 3 for
-    // bonds shorter than four rest lengths); a row tile is kept if any of
-    // its modes has C_p * 6 s_p sqrt(M) >= 2^-30 W_p.
-    const double pi = 3.141592653589793238462643383279502884;
+    // bonds shorter than four rest lengths); row tile J (modes 32J + 1 ..
+    // 32J + 32) is kept if any of its modes has C_p * 6 s_p sqrt(M) >=
+    // 2^-30 W_p.
     int pmax = 0;
     for (int p = 1; p < M; ++p) {
-        const double sp = std::sin(pi * p / (2.0 * M));
+        const double sp = sin_pi_frac(p, 2L * M);
         if (mc.C[p] * 6.0 * sp * std::sqrt((double)M) >= std::ldexp(mc.W[p], -30)) pmax = p;
     }
-    f.JC = std::min(RT, pmax / 32 + 1);
+    f.JC = pmax > 0 ? std::min(RT, (pmax - 1) / 32 + 1) : 0;
+    f.resident = fits_resident(RT, f.JC) ? 1 : 0;
     hipError_t e;
-    if ((e = upload_table(f, 0, M, mc.C.data(), st)) != hipSuccess) return e;
-    if ((e = upload_table(f, 1, M, mc.C.data(), st)) != hipSuccess) return e;
+    if ((e = upload_tables(f, M, mc.C.data(), st)) != hipSuccess) return e;
     e = hipMemcpyAsync(f.d_coef, h.data(), sizeof(float) * h.size(), hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return e;
     return hipStreamSynchronize(st);
 }
 
-template <int RT>
+template <int RT, bool RESIDENT>
 static hipError_t launch_rt(const FusedBucket &f, const FusedArgs &a, hipStream_t st)
 {
     const dim3 grid(nblocks(f.ntiles, 4)), block(256);
     if (f.bf16)
-        hipLaunchKernelGGL((fused_kernel<RT, true>), grid, block, 0, st, a);
+        hipLaunchKernelGGL((fused_kernel<RT, true, RESIDENT>), grid, block, 0, st, a);
     else
-        hipLaunchKernelGGL((fused_kernel<RT, false>), grid, block, 0, st, a);
+        hipLaunchKernelGGL((fused_kernel<RT, false, RESIDENT>), grid, block, 0, st, a);
     return hipGetLastError();
 }
 
@@ -691,7 +778,7 @@ hipError_t fused_step(FusedBucket &f, const int32_t *ids, int M, int n, uint64_t
     a.H = M / 2;
     a.n = n;
     a.ntiles = f.ntiles;
-    a.x_bytes = (int)x_bytes(f.RT, f.bf16 != 0);
+    a.x_bytes = (int)x_bytes(f.RT);
     a.jc = f.JC;
     a.seed = seed;
     a.step0 = step0;
@@ -700,15 +787,17 @@ hipError_t fused_step(FusedBucket &f, const int32_t *ids, int M, int n, uint64_t
     a.lin = f.lin;
     a.W0 = f.W0;
     a.gdt = f.gdt;
+    // the resident form exists where the u = chi R tables fit in LDS
+    // (RT <= 8); it is always taken below RT = 8
     switch (f.RT) {
-    case 2: return launch_rt<2>(f, a, st);
-    case 4: return launch_rt<4>(f, a, st);
-    case 6: return launch_rt<6>(f, a, st);
-    case 8: return launch_rt<8>(f, a, st);
-    case 10: return launch_rt<10>(f, a, st);
-    case 12: return launch_rt<12>(f, a, st);
-    case 14: return launch_rt<14>(f, a, st);
-    case 16: return launch_rt<16>(f, a, st);
+    case 2: return launch_rt<2, true>(f, a, st);
+    case 4: return launch_rt<4, true>(f, a, st);
+    case 6: return launch_rt<6, true>(f, a, st);
+    case 8: return f.resident ? launch_rt<8, true>(f, a, st) : launch_rt<8, false>(f, a, st);
+    case 10: return launch_rt<10, false>(f, a, st);
+    case 12: return launch_rt<12, false>(f, a, st);
+    case 14: return launch_rt<14, false>(f, a, st);
+    case 16: return launch_rt<16, false>(f, a, st);
     default: return hipErrorInvalidValue;
     }
 }
