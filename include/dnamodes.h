@@ -95,6 +95,17 @@ extern "C" {
 #define DM_ACC_MSDCM     6  /* sum of |r_cm - r_cm at the last reset|^2 */
 #define DM_ACC_DMID2     7  /* sum of |r_mid - r_cm|^2 */
 
+/* dm_get_tiling(): DM_NTILING doubles per length bucket. */
+#define DM_NTILING       8
+#define DM_TI_M          0  /* beads per chain */
+#define DM_TI_NCHAINS    1
+#define DM_TI_RT         2  /* 16-row tiles per half transform (fused) */
+#define DM_TI_JC         3  /* coupling row tiles kept (modes p <= 32 JC) */
+#define DM_TI_RESIDENT   4  /* 1: tables held in LDS for a whole launch */
+#define DM_TI_TPW        5  /* tiles of 5 chains per workgroup */
+#define DM_TI_ITEMS      6  /* workgroups of this bucket per launch */
+#define DM_TI_ITEM_US    7  /* measured us per workgroup-step (autotune), or 0 */
+
 typedef struct dm_ctx dm_ctx;
 
 /* Model, time step and run parameters.
@@ -116,6 +127,23 @@ typedef struct {
                                 mode steps (0 = never) */
     int32_t check_finite;    /* 1: after each dm_step_* call check the state
                                 for NaN/Inf and return DM_ENONFINITE */
+    int32_t autotune;        /* fused paths, 1: dm_set_params times every tile
+                                shape of every length bucket on a scratch
+                                copy of the state and keeps the combination
+                                with the shortest schedule (see
+                                dm_get_tiling); 0: fixed shapes */
+    int32_t use_graphs;      /* fused paths with sample_every > 0, 1: whole
+                                sampling blocks (the fused launch, the step
+                                counter and the observables) are captured
+                                once as a HIP graph and replayed */
+    int32_t tiles_per_wg;    /* fused paths: 0 = automatic; 1..4 = tiles of 5
+                                chains per workgroup where the tables are
+                                resident (streamed tables always take 4) */
+    int32_t table_mode;      /* fused paths: 0 = automatic, 1 = tables
+                                resident in LDS, 2 = streamed from L2, each
+                                where that form exists for the length (it
+                                overrides the autotuner); results do not
+                                depend on the tile shape */
 } dm_params;
 
 /* Create a context for n_chains chains; beads[c] >= 2 is the number of beads
@@ -179,6 +207,17 @@ int dm_load_state(dm_ctx *ctx, const void *buf, size_t len);
 /* Global step counter (mode and Euler steps share it: it is the Philox
    step index). */
 int dm_get_step(const dm_ctx *ctx, int64_t *step);
+
+/* Tile shapes of the fused launch (all zero except M and chains for
+   DM_FP64).  Every length bucket advances in the same kernel launch: one
+   workgroup item per tpw tiles of 5 chains, items ordered by decreasing cost
+   so that in-order dispatch to free CUs is a longest-first schedule.  With
+   out == NULL only *n_buckets is set.  Errors: DM_EINVAL if len is below
+   DM_NTILING * n_buckets. */
+int dm_get_tiling(const dm_ctx *ctx, double *out, size_t len, int32_t *n_buckets);
+
+/* Text of the last autotuning (one line per timed tile shape), or "". */
+const char *dm_tuning_report(const dm_ctx *ctx);
 
 /* Synchronise the context's stream. */
 int dm_sync(dm_ctx *ctx);

@@ -35,6 +35,8 @@ DM_NACC_HEAD = 8
 CHAIN_OBS_NAMES = ["bond_mean", "L2", "Lx", "Ly", "Lz", "cmx", "cmy", "cmz",
                    "umx", "umy", "umz", "dmx", "dmy", "dmz", "xspan", "bond2_mean"]
 ACC_NAMES = ["M", "n_chains", "n_samples", "bond", "bond2", "L2", "msd_cm", "dmid2"]
+DM_NTILING = 8
+TILING_NAMES = ["M", "n_chains", "RT", "JC", "resident", "tpw", "items", "item_us"]
 
 
 class DMError(RuntimeError):
@@ -51,13 +53,15 @@ class dm_params(ctypes.Structure):
                 ("n_lengths", ctypes.c_int32),
                 ("lengths", ctypes.POINTER(ctypes.c_int32)),
                 ("dt", ctypes.POINTER(ctypes.c_double)),
-                ("sample_every", ctypes.c_int32), ("check_finite", ctypes.c_int32)]
+                ("sample_every", ctypes.c_int32), ("check_finite", ctypes.c_int32),
+                ("autotune", ctypes.c_int32), ("use_graphs", ctypes.c_int32),
+                ("tiles_per_wg", ctypes.c_int32), ("table_mode", ctypes.c_int32)]
 
 
 EXPORTS = ["dm_init_chains", "dm_set_params", "dm_step_modes", "dm_step_euler",
            "dm_observables", "dm_observables_size", "dm_get_positions", "dm_get_modes",
-           "dm_save_state", "dm_load_state", "dm_get_step", "dm_sync", "dm_destroy",
-           "dm_last_error"]
+           "dm_save_state", "dm_load_state", "dm_get_step", "dm_get_tiling",
+           "dm_tuning_report", "dm_sync", "dm_destroy", "dm_last_error"]
 
 _lib = None
 
@@ -85,6 +89,8 @@ def load(path: str = LIB_PATH):
         "dm_save_state": ([vp, vp, ctypes.POINTER(sz)], ctypes.c_int),
         "dm_load_state": ([vp, vp, sz], ctypes.c_int),
         "dm_get_step": ([vp, ctypes.POINTER(i64)], ctypes.c_int),
+        "dm_get_tiling": ([vp, vp, sz, ctypes.POINTER(i32)], ctypes.c_int),
+        "dm_tuning_report": ([vp], ctypes.c_char_p),
         "dm_sync": ([vp], ctypes.c_int),
         "dm_destroy": ([vp], ctypes.c_int),
         "dm_last_error": ([vp], ctypes.c_char_p),
@@ -149,7 +155,8 @@ class Context:
 
     # ------------------------------------------------------------------ API
     def set_params(self, lengths, dt, T_star=None, nu=None, gamma_dot=0.0, nonlinear=True,
-                   sample_every=0, check_finite=False, physical=None):
+                   sample_every=0, check_finite=False, physical=None, autotune=False,
+                   use_graphs=False, tiles_per_wg=0, table_mode=0):
         """Reduced units by default; physical=dict(lambda_, kappa, kT, a, xi)."""
         p = dm_params()
         if physical:
@@ -166,7 +173,23 @@ class Context:
         p.dt = dts.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         p.sample_every = sample_every
         p.check_finite = 1 if check_finite else 0
+        p.autotune = 1 if autotune else 0
+        p.use_graphs = 1 if use_graphs else 0
+        p.tiles_per_wg = tiles_per_wg
+        p.table_mode = {"auto": 0, "resident": 1, "streamed": 2}.get(table_mode, table_mode)
         self._check(self.lib.dm_set_params(self.h, ctypes.byref(p)))
+
+    def tiling(self) -> list:
+        """Per length bucket: dict of the fused launch's tile shape."""
+        nb = ctypes.c_int32()
+        self._check(self.lib.dm_get_tiling(self.h, None, 0, ctypes.byref(nb)))
+        out = np.zeros(DM_NTILING * nb.value)
+        self._check(self.lib.dm_get_tiling(self.h, out.ctypes.data, out.size, ctypes.byref(nb)))
+        return [dict(zip(TILING_NAMES, out[i * DM_NTILING:(i + 1) * DM_NTILING]))
+                for i in range(nb.value)]
+
+    def tuning_report(self) -> str:
+        return self.lib.dm_tuning_report(self.h).decode()
 
     def step_modes(self, n_steps: int):
         self._check(self.lib.dm_step_modes(self.h, n_steps))

@@ -61,6 +61,16 @@ struct dm_ctx {
     int nonlinear = 1, sample_every = 0, check_finite = 0;
     int64_t step = 0;
     int *d_flag = nullptr;
+    // fused paths: one launch over all buckets, and the captured graph of
+    // one sampling block (fused launch, step-counter advance, observables)
+    dm::FusedPlan plan;
+    int use_graphs = 0, autotune = 0;
+    int64_t *d_step = nullptr;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    int graph_steps = 0;
+    std::string tune_report;
     std::string err;
 };
 
@@ -113,22 +123,72 @@ void free_bucket(Bucket &b)
 bool fused_precision(int p) { return p == DM_FP32 || p == DM_BF16X3; }
 
 // Positions of all chains of a bucket (FP64, bucket order) into b.d_r.
-int bucket_positions(dm_ctx *ctx, Bucket &b)
+int bucket_positions(dm_ctx *ctx, Bucket &b, hipStream_t st)
 {
     if (fused_precision(ctx->precision))
-        DM_HIP(ctx, dm::fused_unpack_modes(b.fused, b.d_R64, b.M, b.n, ctx->stream));
-    DM_HIP(ctx, dm::launch_gemm_f64(b.d_Apos, b.d_R64, b.d_r, b.M, 3 * b.n, ctx->stream));
+        DM_HIP(ctx, dm::fused_unpack_modes(b.fused, b.d_R64, b.M, b.n, st));
+    DM_HIP(ctx, dm::launch_gemm_f64(b.d_Apos, b.d_R64, b.d_r, b.M, 3 * b.n, st));
     return DM_OK;
 }
 
-int observe(dm_ctx *ctx, int accumulate)
+int observe(dm_ctx *ctx, int accumulate, hipStream_t st)
 {
     for (Bucket &b : ctx->buckets) {
-        int rc = bucket_positions(ctx, b);
+        int rc = bucket_positions(ctx, b, st);
         if (rc) return rc;
         DM_HIP(ctx, dm::launch_chain_obs(b.d_r, b.d_R64, b.d_obs, b.d_m2, b.d_acc, b.d_cm0, b.M,
-                                         b.n, accumulate, ctx->stream));
+                                         b.n, accumulate, st));
     }
+    return DM_OK;
+}
+
+void drop_graph(dm_ctx *ctx)
+{
+    if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+    if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+    ctx->graph_exec = nullptr;
+    ctx->graph = nullptr;
+    ctx->graph_steps = 0;
+}
+
+// Capture one sampling block of `steps` fused steps: the launch reads its
+// Philox step from ctx->d_step, a one-thread kernel advances it, then the
+// observables are accumulated.  No memset nodes (plain kernels only).
+int capture_block(dm_ctx *ctx, int steps)
+{
+    drop_graph(ctx);
+    if (!ctx->cap_stream)
+        DM_HIP(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+    DM_HIP(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = dm::fused_launch(ctx->plan, ctx->seed, 0, ctx->d_step, steps, ctx->nonlinear,
+                                    ctx->cap_stream);
+    if (e == hipSuccess) e = dm::fused_advance_step(ctx->d_step, steps, ctx->cap_stream);
+    int rc = e == hipSuccess ? observe(ctx, 1, ctx->cap_stream) : DM_OK;
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(ctx->cap_stream, &g);
+    if (e != hipSuccess || rc != DM_OK || ec != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        if (rc != DM_OK) return rc;
+        return fail(ctx, DM_EHIP, "graph capture failed: %s",
+                    hipGetErrorString(e != hipSuccess ? e : ec));
+    }
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return fail(ctx, DM_EHIP, "hipGraphInstantiate failed: %s", hipGetErrorString(e));
+    }
+    ctx->graph = g;
+    ctx->graph_exec = x;
+    ctx->graph_steps = steps;
+    return DM_OK;
+}
+
+int build_plan(dm_ctx *ctx)
+{
+    std::vector<const dm::FusedBucket *> fb;
+    for (Bucket &b : ctx->buckets) fb.push_back(&b.fused);
+    DM_HIP(ctx, dm::fused_plan(ctx->plan, fb, 0, ctx->stream));
     return DM_OK;
 }
 
@@ -225,11 +285,13 @@ int dm_init_chains(dm_ctx **out, int32_t n_chains, const int32_t *beads, const d
         std::string msg = ctx->err;
         for (Bucket &b : ctx->buckets) free_bucket(b);
         if (ctx->d_flag) (void)hipFree(ctx->d_flag);
+        if (ctx->d_step) (void)hipFree(ctx->d_step);
         delete ctx;
         g_init_error = msg;
         return code;
     };
     if ((rc = dalloc(ctx, &ctx->d_flag, 1))) return bail(rc);
+    if ((rc = dalloc(ctx, &ctx->d_step, 1))) return bail(rc);
     std::vector<double> phi, tmp;
     for (Bucket &b : ctx->buckets) {
         const size_t MM = (size_t)b.M * b.M, S = (size_t)3 * b.M * b.n;
@@ -279,6 +341,7 @@ int dm_init_chains(dm_ctx **out, int32_t n_chains, const int32_t *beads, const d
             e = dm::launch_gemm_f64(b.d_Afwd, b.d_r, b.d_R64, b.M, 3 * b.n, ctx->stream);
         if (e == hipSuccess && fused_precision(precision)) {
             e = dm::fused_alloc(b.fused, b.M, b.n, precision == DM_BF16X3);
+            b.fused.ids = b.d_ids;
             if (e == hipSuccess) e = dm::fused_pack_modes(b.fused, b.d_R64, b.M, b.n, ctx->stream);
         }
         // the host staging buffers die with this scope: finish the uploads first
@@ -315,6 +378,8 @@ int dm_set_params(dm_ctx *ctx, const dm_params *p)
     if (p->n_lengths <= 0 || !p->lengths || !p->dt)
         return fail(ctx, DM_EINVAL, "lengths / dt tables are empty");
     if (p->sample_every < 0) return fail(ctx, DM_EINVAL, "sample_every must be >= 0");
+    if (p->tiles_per_wg < 0 || p->tiles_per_wg > 4 || p->table_mode < 0 || p->table_mode > 2)
+        return fail(ctx, DM_EINVAL, "tiles_per_wg must be 0..4 and table_mode 0..2");
     std::vector<double> dtau(ctx->buckets.size());
     for (size_t i = 0; i < ctx->buckets.size(); ++i) {
         int found = -1;
@@ -352,6 +417,22 @@ int dm_set_params(dm_ctx *ctx, const dm_params *p)
     ctx->nonlinear = p->nonlinear ? 1 : 0;
     ctx->sample_every = p->sample_every;
     ctx->check_finite = p->check_finite ? 1 : 0;
+    ctx->use_graphs = p->use_graphs ? 1 : 0;
+    ctx->autotune = p->autotune ? 1 : 0;
+    drop_graph(ctx);  // captured launches hold the old tables and plan
+    if (fused_precision(ctx->precision)) {
+        ctx->tune_report.clear();
+        if (ctx->autotune) {
+            std::vector<dm::FusedBucket *> fb;
+            for (Bucket &b : ctx->buckets) fb.push_back(&b.fused);
+            DM_HIP(ctx, dm::fused_autotune(fb, ctx->seed, 64, ctx->stream, ctx->tune_report));
+        }
+        if (p->tiles_per_wg || p->table_mode)
+            for (Bucket &b : ctx->buckets)
+                dm::fused_force_shape(b.fused, p->table_mode, p->tiles_per_wg);
+        int rc = build_plan(ctx);
+        if (rc) return rc;
+    }
     ctx->have_params = true;
     return DM_OK;
 }
@@ -362,7 +443,23 @@ int dm_step_modes(dm_ctx *ctx, int64_t n_steps)
     if (!ctx->have_params) return fail(ctx, DM_ESTATE, "dm_set_params has not been called");
     if (n_steps < 0) return fail(ctx, DM_EINVAL, "n_steps must be >= 0");
     int64_t done = 0;
+    const bool graphs = fused_precision(ctx->precision) && ctx->use_graphs && ctx->sample_every > 0;
     while (done < n_steps) {
+        const int se = ctx->sample_every;
+        if (graphs && ctx->step % se == 0 && n_steps - done >= se) {
+            // whole sampling blocks: replay the captured block
+            if (!ctx->graph_exec || ctx->graph_steps != se) {
+                int rc = capture_block(ctx, se);
+                if (rc) return rc;
+            }
+            const int64_t blocks = (n_steps - done) / se;
+            DM_HIP(ctx, dm::fused_set_step(ctx->d_step, ctx->step, ctx->stream));
+            for (int64_t i = 0; i < blocks; ++i)
+                DM_HIP(ctx, hipGraphLaunch(ctx->graph_exec, ctx->stream));
+            ctx->step += blocks * se;
+            done += blocks * se;
+            continue;
+        }
         // steps until the next sampling point (or the end of the request)
         int64_t chunk = n_steps - done;
         if (ctx->sample_every > 0) {
@@ -370,10 +467,9 @@ int dm_step_modes(dm_ctx *ctx, int64_t n_steps)
             chunk = std::min(chunk, to_sample);
         }
         if (fused_precision(ctx->precision)) {
-            for (Bucket &b : ctx->buckets)
-                DM_HIP(ctx, dm::fused_step(b.fused, b.d_ids, b.M, b.n, ctx->seed, ctx->step,
-                                           (int)std::min<int64_t>(chunk, 1 << 30),
-                                           ctx->nonlinear, ctx->stream));
+            chunk = std::min<int64_t>(chunk, 1 << 30);
+            DM_HIP(ctx, dm::fused_launch(ctx->plan, ctx->seed, ctx->step, nullptr, (int)chunk,
+                                         ctx->nonlinear, ctx->stream));
         } else {
             for (int64_t s = 0; s < chunk; ++s)
                 for (Bucket &b : ctx->buckets) {
@@ -384,7 +480,7 @@ int dm_step_modes(dm_ctx *ctx, int64_t n_steps)
         ctx->step += chunk;
         done += chunk;
         if (ctx->sample_every > 0 && ctx->step % ctx->sample_every == 0) {
-            int rc = observe(ctx, 1);
+            int rc = observe(ctx, 1, ctx->stream);
             if (rc) return rc;
         }
     }
@@ -401,7 +497,7 @@ int dm_step_euler(dm_ctx *ctx, int64_t n_steps, double dtau)
     if (n_steps == 0) return DM_OK;
     const double gdt = ctx->gamma_dot * dtau;
     for (Bucket &b : ctx->buckets) {
-        int rc = bucket_positions(ctx, b);  // b.d_r = phi R (all modes, FP64)
+        int rc = bucket_positions(ctx, b, ctx->stream);  // b.d_r = phi R (all modes, FP64)
         if (rc) return rc;
         DM_HIP(ctx, dm::launch_euler_f64(b.d_r, b.d_ids, b.M, b.n, ctx->nu, dtau, ctx->T_star,
                                          gdt, ctx->seed, ctx->step, (int)n_steps, ctx->stream));
@@ -435,7 +531,7 @@ int dm_observables(dm_ctx *ctx, int32_t which, double *out_host, size_t out_len)
         return fail(ctx, DM_EINVAL, "output needs %zu doubles, got %zu", need, out_len);
     double *o = out_host;
     if (which & (DM_OBS_CHAIN | DM_OBS_MODES)) {
-        int rc = observe(ctx, 0);
+        int rc = observe(ctx, 0, ctx->stream);
         if (rc) return rc;
         DM_HIP(ctx, hipStreamSynchronize(ctx->stream));
     }
@@ -476,7 +572,7 @@ int dm_observables(dm_ctx *ctx, int32_t which, double *out_host, size_t out_len)
     }
     if (which & DM_OBS_RESET) {
         // the MSD reference becomes the current centre of mass
-        int rc = observe(ctx, 0);
+        int rc = observe(ctx, 0, ctx->stream);
         if (rc) return rc;
         for (Bucket &b : ctx->buckets) {
             DM_HIP(ctx, hipMemsetAsync(b.d_acc, 0, sizeof(double) * (8 + b.M) * b.n,
@@ -494,7 +590,7 @@ int dm_get_positions(dm_ctx *ctx, double *dst, int32_t dst_on_device)
 {
     if (!ctx || !dst) return ctx ? fail(ctx, DM_EINVAL, "dst is NULL") : DM_EINVAL;
     for (Bucket &b : ctx->buckets) {
-        int rc = bucket_positions(ctx, b);
+        int rc = bucket_positions(ctx, b, ctx->stream);
         if (rc) return rc;
         if (dst_on_device) {
             DM_HIP(ctx, dm::launch_scatter_chains(b.d_r, dst, b.d_off, 3 * b.M, b.n,
@@ -633,11 +729,42 @@ int dm_destroy(dm_ctx *ctx)
 {
     if (!ctx) return DM_EINVAL;
     (void)hipStreamSynchronize(ctx->stream);
+    drop_graph(ctx);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+    dm::fused_plan_free(ctx->plan);
     for (Bucket &b : ctx->buckets) free_bucket(b);
     if (ctx->d_flag) (void)hipFree(ctx->d_flag);
+    if (ctx->d_step) (void)hipFree(ctx->d_step);
     delete ctx;
     return DM_OK;
 }
+
+int dm_get_tiling(const dm_ctx *ctx, double *out, size_t len, int32_t *n_buckets)
+{
+    if (!ctx || !n_buckets) return DM_EINVAL;
+    *n_buckets = (int32_t)ctx->buckets.size();
+    if (!out) return DM_OK;
+    if (len < (size_t)DM_NTILING * ctx->buckets.size())
+        return fail(const_cast<dm_ctx *>(ctx), DM_EINVAL, "tiling needs %zu doubles",
+                    (size_t)DM_NTILING * ctx->buckets.size());
+    const bool fused = fused_precision(ctx->precision);
+    for (size_t i = 0; i < ctx->buckets.size(); ++i) {
+        const Bucket &b = ctx->buckets[i];
+        const dm::FusedBucket &f = b.fused;
+        double *o = out + DM_NTILING * i;
+        o[DM_TI_M] = b.M;
+        o[DM_TI_NCHAINS] = b.n;
+        o[DM_TI_RT] = fused ? f.RT : 0;
+        o[DM_TI_JC] = fused ? f.JC : 0;
+        o[DM_TI_RESIDENT] = fused ? f.resident : 0;
+        o[DM_TI_TPW] = fused ? f.tpw : 0;
+        o[DM_TI_ITEMS] = fused ? (f.ntiles + f.tpw - 1) / f.tpw : 0;
+        o[DM_TI_ITEM_US] = fused ? f.item_us : 0;
+    }
+    return DM_OK;
+}
+
+const char *dm_tuning_report(const dm_ctx *ctx) { return ctx ? ctx->tune_report.c_str() : ""; }
 
 const char *dm_last_error(const dm_ctx *ctx)
 {

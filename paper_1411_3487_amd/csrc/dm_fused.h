@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string>
 #include <vector>
 
 #include "dm_tables.h"
@@ -21,6 +22,10 @@ struct FusedBucket {
     double *d_sig = nullptr; // sigma_p of the even modes, by half-mode slot
     int JC = 0;              // coupling row tiles with non-negligible C_p
     int resident = 0;        // tables held in LDS for the whole launch
+    int tpw = 4;             // tiles per workgroup (1..4; 4 when streamed)
+    double item_us = 0.0;    // measured time of one workgroup-step (0: model)
+    int n = 0;               // chains
+    const int32_t *ids = nullptr;  // device: global chain index per local chain
     double W0 = 0.0, gdt = 0.0;
     float lin = 0.0f;
     std::vector<double> Xo, Se, sig;  // host FP64 half tables (the coupling
@@ -34,8 +39,33 @@ hipError_t fused_pack_modes(FusedBucket &f, const double *R64, int M, int n, hip
 hipError_t fused_unpack_modes(const FusedBucket &f, double *R64, int M, int n, hipStream_t st);
 hipError_t fused_set_coefs(FusedBucket &f, const ModeCoefs &mc, int M, double lin, double gdt,
                            hipStream_t st);
-hipError_t fused_step(FusedBucket &f, const int32_t *ids, int M, int n, uint64_t seed,
-                      int64_t step0, int n_steps, int nonlinear, hipStream_t st);
+
+// One launch over all buckets: a list of workgroup items, longest first.
+struct FusedPlan {
+    int bf16 = 0, nitems = 0, nbuckets = 0;
+    void *d_buckets = nullptr, *d_items = nullptr;
+};
+// Build the launch for the buckets (all of one precision) with their current
+// tile shapes; max_items > 0 keeps only the first items (timing).
+hipError_t fused_plan(FusedPlan &p, const std::vector<const FusedBucket *> &bs, int max_items,
+                      hipStream_t st);
+void fused_plan_free(FusedPlan &p);
+// n_steps mode steps of every bucket of the plan; the Philox step of the
+// first step is *d_step when d_step is non-null (read on the device, for
+// replayed graphs), else step0.
+hipError_t fused_launch(const FusedPlan &p, uint64_t seed, int64_t step0, const int64_t *d_step,
+                        int n_steps, int nonlinear, hipStream_t st);
+// Time every tile shape of every bucket on a scratch copy of its state and
+// keep the combination with the shortest list-schedule makespan.  One line
+// per candidate goes to report.
+hipError_t fused_autotune(std::vector<FusedBucket *> &bs, uint64_t seed, int steps,
+                          hipStream_t st, std::string &report);
+// Force a tile shape where it exists: table_mode 1 resident, 2 streamed (0
+// keeps the current); tpw 1..4 where resident (0 keeps the current).
+void fused_force_shape(FusedBucket &f, int table_mode, int tpw);
+// Device step counter of replayed graphs: *d_step = value, *d_step += n.
+hipError_t fused_set_step(int64_t *d_step, int64_t value, hipStream_t st);
+hipError_t fused_advance_step(int64_t *d_step, int64_t n, hipStream_t st);
 hipError_t fused_check_finite(const FusedBucket &f, int M, int n, int *flag, hipStream_t st);
 
 }  // namespace dm

@@ -45,6 +45,9 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <functional>
+#include <string>
 #include <vector>
 
 #include "dm_fused.h"
@@ -62,18 +65,30 @@ constexpr int kChainsPerTile = 5;
 // mode E, W, gdt E; even mode E, sigma W, gdt E, sigma^2 C.
 enum { kEo, kWo, kGo, kEe, kWe, kGe, kCe, kKinds };
 
-struct FusedArgs {
-    const void *X;
-    float *R;
-    double *R0;
-    const float *coef;
-    const int32_t *ids;
-    int M, H, n, ntiles, x_bytes, jc;
-    uint64_t seed;
-    int64_t step0;
-    int n_steps, nonlinear;
+// One length bucket as the kernel sees it (read from device memory).
+struct BucketArgs {
+    const void *X;        // transform tables, fragment order
+    float *R;             // internal mode amplitudes, fragment order
+    double *R0;           // centre-of-mass mode, 16 doubles per tile
+    const float *coef;    // [kind][16 RT] update coefficients
+    const int32_t *ids;   // global chain index of each local chain
+    int n, ntiles, x_bytes, jc, variant, tpw;
     float lin;
     double W0, gdt;
+};
+
+// One workgroup of a launch: tiles tile0 .. tile0 + tpw - 1 of one bucket.
+struct Item {
+    int bucket, tile0;
+};
+
+struct LaunchArgs {
+    const BucketArgs *buckets;
+    const Item *items;
+    const int64_t *step;  // Philox step of the first step, or null: step0
+    int64_t step0;
+    uint64_t seed;
+    int n_steps, nonlinear;
 };
 
 // DPP lane moves inside a 16-lane row (out-of-row sources read 0):
@@ -209,7 +224,8 @@ __device__ __forceinline__ uint32_t after(uint32_t x, float d)
 constexpr int kTableFrags = 152;  // LDS for transform tables, in 1 KB fragments
 
 template <int RT, bool BF16, bool RESIDENT>
-__global__ __launch_bounds__(256) void fused_kernel(FusedArgs a)
+__device__ __forceinline__ void fused_tiles(const BucketArgs &a, const LaunchArgs &la, int tile0,
+                                            int64_t step0, f32x4 *cf, f32x4 *xb)
 {
     constexpr int KS = RT / 2;
     constexpr int SF = 2 * RT;    // fragments per stage
@@ -220,8 +236,7 @@ __global__ __launch_bounds__(256) void fused_kernel(FusedArgs a)
     static_assert(!RESIDENT || G1 + RT <= kTableFrags, "resident tables exceed LDS");
     static_assert(RESIDENT || (NB >= 3 && (DIST - 1) * (SF / 4) < 64), "stream buffers");
     const int NS = RT + a.jc;  // stages per step when streaming
-    __shared__ f32x4 cf[kKinds * RT * 4];  // [kind][J][g], four slots r each
-    __shared__ f32x4 xb[kTableFrags * 64];
+    // cf: [kind][J][g], four slots r each; xb: table fragments
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     {
@@ -229,8 +244,9 @@ __global__ __launch_bounds__(256) void fused_kernel(FusedArgs a)
         for (int i = threadIdx.x; i < kKinds * RT * 4; i += blockDim.x) cf[i] = c4[i];
     }
 
-    const int tile = blockIdx.x * 4 + wave;
-    const bool has_tile = tile < a.ntiles;  // idle waves still stage and sync
+    const int tile = tile0 + wave;
+    // idle waves still stage (and, when streaming, synchronise)
+    const bool has_tile = wave < a.tpw && tile < a.ntiles;
     const int col = lane & 15, g = lane >> 4;
     const int cl = col / 3, alpha = col - 3 * cl;
     const int nvalid = has_tile ? min(kChainsPerTile, a.n - kChainsPerTile * tile) : 0;
@@ -254,7 +270,7 @@ __global__ __launch_bounds__(256) void fused_kernel(FusedArgs a)
     // streaming: stage t of any step lives in buffer (b0 + t) % NB; b0
     // advances by NS per step
     int b0 = 0;
-    if (a.nonlinear) {
+    if (la.nonlinear) {
         if constexpr (RESIDENT) {
             copy_frags(xrs, 0, xb, G1, wave, lane_bytes);
             for (int J = 0; J < a.jc; ++J)  // odd halves of the coupling stages
@@ -265,7 +281,7 @@ __global__ __launch_bounds__(256) void fused_kernel(FusedArgs a)
             // has fewer stages than the prefetch distance)
             int issued = 0;
             for (int t = 0; t < DIST; ++t)
-                if (t / NS < a.n_steps) {
+                if (t / NS < la.n_steps) {
                     stage<SF>(xrs, (t % NS) * SF, xb + (t % NB) * SF * 64, wave, lane_bytes);
                     ++issued;
                 }
@@ -276,6 +292,9 @@ __global__ __launch_bounds__(256) void fused_kernel(FusedArgs a)
         }
     }
     __syncthreads();
+    if constexpr (RESIDENT) {
+        if (!has_tile) return;  // no barrier follows
+    }
 
     // Streaming: issue the copy of stage t + DIST (of this step or, wrapping,
     // of the next) and, after the compute of stage t, wait until stage t + 1
@@ -285,7 +304,7 @@ __global__ __launch_bounds__(256) void fused_kernel(FusedArgs a)
             // stage t + DIST counted from the start of this step, as (step
             // ahead, stage of that step); nothing beyond the last step
             const int tn = t + DIST;
-            if (s + tn / NS < a.n_steps)
+            if (s + tn / NS < la.n_steps)
                 stage<SF>(xrs, (tn % NS) * SF, xb + ((b0 + tn) % NB) * SF * 64, wave, lane_bytes);
         }
     };
@@ -294,7 +313,7 @@ __global__ __launch_bounds__(256) void fused_kernel(FusedArgs a)
     auto finish = [&](int t, int s) {
         if constexpr (!RESIDENT) {
             // last stage issued so far, counted from the start of this step
-            const int last = min(t + DIST, (a.n_steps - s) * NS - 1);
+            const int last = min(t + DIST, (la.n_steps - s) * NS - 1);
             const int ahead = last - (t + 1);  // issued beyond t+1
             if (ahead >= DIST - 1)
                 wait_vmcnt<(DIST - 1) * (SF / 4)>();
@@ -309,11 +328,11 @@ __global__ __launch_bounds__(256) void fused_kernel(FusedArgs a)
         else
             return xb + ((b0 + t) % NB) * SF * 64;
     };
-    for (int s = 0; s < a.n_steps; ++s) {
-        const int64_t k = a.step0 + s;
+    for (int s = 0; s < la.n_steps; ++s) {
+        const int64_t k = step0 + s;
         f32x4 Gp[RT], Gm[RT];
         [[maybe_unused]] bf16x8 gph[KS], gpl[KS], gmh[KS], gml[KS];
-        if (a.nonlinear) {
+        if (la.nonlinear) {
             // ---- u = chi R: half-bond rows I, K over mode slabs q
             f32x4 aS[RT], aA[RT];
 #pragma unroll
@@ -386,15 +405,15 @@ __global__ __launch_bounds__(256) void fused_kernel(FusedArgs a)
 #pragma unroll
         for (int J = 0; J < RT; ++J) {
             const int t = RT + J;
-            const bool couple = a.nonlinear && J < a.jc;
+            const bool couple = la.nonlinear && J < a.jc;
             if (couple) prefetch(t, s);
             const uint32_t ch =
-                after(chain, J ? Ro[J - 1][3] : (a.nonlinear ? Gm[0][0] : Re[0][0]));
+                after(chain, J ? Ro[J - 1][3] : (la.nonlinear ? Gm[0][0] : Re[0][0]));
             float z[8];
-            normals4_f32(noise_bits(a.seed, (uint32_t)(8 * J + 2 * g), ch, k, (uint32_t)alpha,
+            normals4_f32(noise_bits(la.seed, (uint32_t)(8 * J + 2 * g), ch, k, (uint32_t)alpha,
                                     kTagMode),
                          z);
-            normals4_f32(noise_bits(a.seed, (uint32_t)(8 * J + 2 * g + 1), ch, k,
+            normals4_f32(noise_bits(la.seed, (uint32_t)(8 * J + 2 * g + 1), ch, k,
                                     (uint32_t)alpha, kTagMode),
                          z + 4);
             const float zn = __shfl(z[0], (lane + 16) & 63, 64);
@@ -488,6 +507,38 @@ __global__ __launch_bounds__(256) void fused_kernel(FusedArgs a)
     }
     if (com_lane) a.R0[(size_t)tile * 16 + col] = r0;
 }
+
+constexpr int kCoefF4 = kKinds * 16 * 4;  // coefficients of the largest tiles
+
+// The launch: each workgroup runs one item, on the tile shape of its bucket.
+// Items are ordered longest first, so the hardware's in-order dispatch of
+// workgroups to free CUs is a longest-processing-time schedule.
+template <bool BF16>
+__global__ __launch_bounds__(256) void fused_kernel(LaunchArgs la)
+{
+    __shared__ f32x4 lds[kCoefF4 + kTableFrags * 64];
+    const Item it = la.items[blockIdx.x];
+    const BucketArgs a = la.buckets[it.bucket];
+    const int64_t step0 = la.step ? *la.step : la.step0;
+    f32x4 *cf = lds, *xb = lds + kCoefF4;
+    switch (a.variant) {
+    case 0: fused_tiles<2, BF16, true>(a, la, it.tile0, step0, cf, xb); break;
+    case 1: fused_tiles<4, BF16, true>(a, la, it.tile0, step0, cf, xb); break;
+    case 2: fused_tiles<6, BF16, true>(a, la, it.tile0, step0, cf, xb); break;
+    case 3: fused_tiles<8, BF16, true>(a, la, it.tile0, step0, cf, xb); break;
+    case 4: fused_tiles<8, BF16, false>(a, la, it.tile0, step0, cf, xb); break;
+    case 5: fused_tiles<10, BF16, false>(a, la, it.tile0, step0, cf, xb); break;
+    case 6: fused_tiles<12, BF16, false>(a, la, it.tile0, step0, cf, xb); break;
+    case 7: fused_tiles<14, BF16, false>(a, la, it.tile0, step0, cf, xb); break;
+    case 8: fused_tiles<16, BF16, false>(a, la, it.tile0, step0, cf, xb); break;
+    default: break;
+    }
+}
+
+// Kernel variant of a tile shape: resident tables exist for RT <= 8,
+// streamed ones for RT >= 8.
+int variant_of(int RT, bool resident) { return resident ? RT / 2 - 1 : 4 + (RT - 8) / 2; }
+bool has_variant(int RT, bool resident) { return resident ? RT <= 8 : RT >= 8; }
 
 // Slot of mode p >= 1 of (local chain j, component alpha) in the state:
 // odd p at half-mode slot (p - 1)/2, even p at p/2 - 1.
@@ -584,6 +635,7 @@ hipError_t fused_alloc(FusedBucket &f, int M, int n, bool bf16)
     f.bf16 = bf16 ? 1 : 0;
     f.RT = rt_of(M);
     f.ntiles = tiles_of(n);
+    f.n = n;
     const int RT = f.RT, H = M / 2, Hp = 16 * RT;
     // half-bond x half-mode tables, bond row i <-> bond i + 1:
     //   Xo[i][j] = chi_{i+1, 2j+1} = sigma_{2j+1} sin((i+1)(2j+1) pi/M)
@@ -746,6 +798,8 @@ hipError_t fused_set_coefs(FusedBucket &f, const ModeCoefs &mc, int M, double li
     }
     f.JC = pmax > 0 ? std::min(RT, (pmax - 1) / 32 + 1) : 0;
     f.resident = fits_resident(RT, f.JC) ? 1 : 0;
+    f.tpw = 4;  // default shape; timings of other coefficients are stale
+    f.item_us = 0.0;
     hipError_t e;
     if ((e = upload_tables(f, M, mc.C.data(), st)) != hipSuccess) return e;
     e = hipMemcpyAsync(f.d_coef, h.data(), sizeof(float) * h.size(), hipMemcpyHostToDevice, st);
@@ -753,53 +807,306 @@ hipError_t fused_set_coefs(FusedBucket &f, const ModeCoefs &mc, int M, double li
     return hipStreamSynchronize(st);
 }
 
-template <int RT, bool RESIDENT>
-static hipError_t launch_rt(const FusedBucket &f, const FusedArgs &a, hipStream_t st)
+static BucketArgs bucket_args(const FusedBucket &f)
 {
-    const dim3 grid(nblocks(f.ntiles, 4)), block(256);
-    if (f.bf16)
-        hipLaunchKernelGGL((fused_kernel<RT, true, RESIDENT>), grid, block, 0, st, a);
-    else
-        hipLaunchKernelGGL((fused_kernel<RT, false, RESIDENT>), grid, block, 0, st, a);
-    return hipGetLastError();
-}
-
-hipError_t fused_step(FusedBucket &f, const int32_t *ids, int M, int n, uint64_t seed,
-                      int64_t step0, int n_steps, int nonlinear, hipStream_t st)
-{
-    if (n_steps <= 0 || n <= 0) return hipSuccess;
-    FusedArgs a;
+    BucketArgs a;
     a.X = f.d_X;
     a.R = f.d_R;
     a.R0 = f.d_R0;
     a.coef = f.d_coef;
-    a.ids = ids;
-    a.M = M;
-    a.H = M / 2;
-    a.n = n;
+    a.ids = f.ids;
+    a.n = f.n;
     a.ntiles = f.ntiles;
     a.x_bytes = (int)x_bytes(f.RT);
     a.jc = f.JC;
-    a.seed = seed;
-    a.step0 = step0;
-    a.n_steps = n_steps;
-    a.nonlinear = nonlinear;
+    a.variant = variant_of(f.RT, f.resident != 0);
+    a.tpw = f.tpw;
     a.lin = f.lin;
     a.W0 = f.W0;
     a.gdt = f.gdt;
-    // the resident form exists where the u = chi R tables fit in LDS
-    // (RT <= 8); it is always taken below RT = 8
-    switch (f.RT) {
-    case 2: return launch_rt<2, true>(f, a, st);
-    case 4: return launch_rt<4, true>(f, a, st);
-    case 6: return launch_rt<6, true>(f, a, st);
-    case 8: return f.resident ? launch_rt<8, true>(f, a, st) : launch_rt<8, false>(f, a, st);
-    case 10: return launch_rt<10, false>(f, a, st);
-    case 12: return launch_rt<12, false>(f, a, st);
-    case 14: return launch_rt<14, false>(f, a, st);
-    case 16: return launch_rt<16, false>(f, a, st);
-    default: return hipErrorInvalidValue;
+    return a;
+}
+
+// Cost model of one workgroup-step when nothing was measured: the MFMA and
+// table work grow as RT^2, the noise and forces as RT.
+static double model_us(const FusedBucket &f)
+{
+    const double rt = f.RT;
+    return 0.12 * rt * rt + 0.3 * rt + (f.resident ? 0.0 : 0.02 * rt * rt);
+}
+
+// Items of the given buckets, longest first (ties in bucket, tile order).
+static std::vector<Item> ordered_items(const std::vector<const FusedBucket *> &bs,
+                                       std::vector<double> *cost = nullptr)
+{
+    std::vector<std::pair<double, Item>> v;
+    for (size_t b = 0; b < bs.size(); ++b) {
+        const FusedBucket &f = *bs[b];
+        const double c = f.item_us > 0.0 ? f.item_us : model_us(f);
+        for (int t = 0; t < f.ntiles; t += f.tpw) v.push_back({c, Item{(int)b, t}});
     }
+    std::stable_sort(v.begin(), v.end(),
+                     [](const std::pair<double, Item> &x, const std::pair<double, Item> &y) {
+                         return x.first > y.first;
+                     });
+    std::vector<Item> out;
+    out.reserve(v.size());
+    if (cost) cost->clear();
+    for (auto &e : v) {
+        out.push_back(e.second);
+        if (cost) cost->push_back(e.first);
+    }
+    return out;
+}
+
+void fused_plan_free(FusedPlan &p)
+{
+    if (p.d_buckets) (void)hipFree(p.d_buckets);
+    if (p.d_items) (void)hipFree(p.d_items);
+    p = FusedPlan();
+}
+
+// The bodies of all tile shapes are inlined into the one launch kernel, whose
+// private (spill) segment must stay within the HIP runtime's default
+// per-thread stack of 1 KB: a larger segment is refused here rather than
+// launched.
+constexpr size_t kMaxPrivateBytes = 1024;
+static hipError_t check_private_segment(bool bf16)
+{
+    hipFuncAttributes at;
+    const void *fn = bf16 ? reinterpret_cast<const void *>(&fused_kernel<true>)
+                          : reinterpret_cast<const void *>(&fused_kernel<false>);
+    hipError_t e = hipFuncGetAttributes(&at, fn);
+    if (e != hipSuccess) return e;
+    return at.localSizeBytes <= kMaxPrivateBytes ? hipSuccess : hipErrorInvalidConfiguration;
+}
+
+hipError_t fused_plan(FusedPlan &p, const std::vector<const FusedBucket *> &bs, int max_items,
+                      hipStream_t st)
+{
+    fused_plan_free(p);
+    if (bs.empty()) return hipSuccess;
+    p.bf16 = bs[0]->bf16;
+    hipError_t e = check_private_segment(p.bf16 != 0);
+    if (e != hipSuccess) return e;
+    std::vector<BucketArgs> ba;
+    for (const FusedBucket *f : bs) {
+        if (f->bf16 != p.bf16) return hipErrorInvalidValue;
+        if (!has_variant(f->RT, f->resident != 0) || f->tpw < 1 || f->tpw > 4 ||
+            (!f->resident && f->tpw != 4))
+            return hipErrorInvalidValue;
+        ba.push_back(bucket_args(*f));
+    }
+    std::vector<Item> items = ordered_items(bs);
+    if (max_items > 0 && (int)items.size() > max_items) items.resize(max_items);
+    p.nitems = (int)items.size();
+    p.nbuckets = (int)bs.size();
+    if ((e = hipMalloc(&p.d_buckets, sizeof(BucketArgs) * ba.size())) != hipSuccess) return e;
+    if ((e = hipMalloc(&p.d_items, sizeof(Item) * std::max<size_t>(1, items.size()))) !=
+        hipSuccess)
+        return e;
+    if ((e = hipMemcpyAsync(p.d_buckets, ba.data(), sizeof(BucketArgs) * ba.size(),
+                            hipMemcpyHostToDevice, st)) != hipSuccess)
+        return e;
+    if ((e = hipMemcpyAsync(p.d_items, items.data(), sizeof(Item) * items.size(),
+                            hipMemcpyHostToDevice, st)) != hipSuccess)
+        return e;
+    return hipStreamSynchronize(st);  // the host vectors die here
+}
+
+hipError_t fused_launch(const FusedPlan &p, uint64_t seed, int64_t step0, const int64_t *d_step,
+                        int n_steps, int nonlinear, hipStream_t st)
+{
+    if (n_steps <= 0 || p.nitems == 0) return hipSuccess;
+    LaunchArgs la;
+    la.buckets = static_cast<const BucketArgs *>(p.d_buckets);
+    la.items = static_cast<const Item *>(p.d_items);
+    la.step = d_step;
+    la.step0 = step0;
+    la.seed = seed;
+    la.n_steps = n_steps;
+    la.nonlinear = nonlinear;
+    if (p.bf16)
+        hipLaunchKernelGGL(fused_kernel<true>, dim3(p.nitems), dim3(256), 0, st, la);
+    else
+        hipLaunchKernelGGL(fused_kernel<false>, dim3(p.nitems), dim3(256), 0, st, la);
+    return hipGetLastError();
+}
+
+// Makespan of a longest-first list schedule of the items on ncu CUs (one
+// workgroup per CU: the tables take the LDS).
+static double makespan(const std::vector<double> &cost, int ncu)
+{
+    std::vector<double> load((size_t)std::max(1, ncu), 0.0);
+    double m = 0.0;
+    for (double c : cost) {  // cost is sorted longest first
+        auto it = std::min_element(load.begin(), load.end());
+        *it += c;
+        m = std::max(m, *it);
+    }
+    return m;
+}
+
+hipError_t fused_autotune(std::vector<FusedBucket *> &bs, uint64_t seed, int steps,
+                          hipStream_t st, std::string &report)
+{
+    int dev = 0, ncu = 256;
+    hipError_t e;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+    if ((e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev)) !=
+        hipSuccess)
+        return e;
+    if (steps < 1) steps = 64;
+    struct Cand {
+        int resident, tpw;
+        double us;  // per workgroup-step
+    };
+    std::vector<std::vector<Cand>> cands(bs.size());
+    hipEvent_t e0, e1;
+    if ((e = hipEventCreate(&e0)) != hipSuccess) return e;
+    if ((e = hipEventCreate(&e1)) != hipSuccess) return e;
+    for (size_t b = 0; b < bs.size() && e == hipSuccess; ++b) {
+        FusedBucket &f = *bs[b];
+        // time each shape on a scratch copy of the state (the tables and
+        // coefficients are shared, the state is not touched)
+        FusedBucket t = f;
+        t.d_R = nullptr;
+        t.d_R0 = nullptr;
+        const size_t nR = sizeof(float) * state_floats(f.RT, f.ntiles);
+        const size_t nR0 = sizeof(double) * 16 * (size_t)f.ntiles;
+        if ((e = hipMalloc((void **)&t.d_R, nR)) != hipSuccess) break;
+        if ((e = hipMalloc((void **)&t.d_R0, nR0)) != hipSuccess) {
+            (void)hipFree(t.d_R);
+            break;
+        }
+        e = hipMemcpyAsync(t.d_R, f.d_R, nR, hipMemcpyDeviceToDevice, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(t.d_R0, f.d_R0, nR0, hipMemcpyDeviceToDevice, st);
+        std::vector<Cand> list;
+        for (int res = 1; res >= 0; --res) {
+            if (!has_variant(f.RT, res) || (res && !fits_resident(f.RT, f.JC))) continue;
+            for (int tpw : {4, 2, 1}) {
+                if (!res && tpw != 4) continue;
+                list.push_back({res, tpw, 0.0});
+            }
+        }
+        for (Cand &c : list) {
+            if (e != hipSuccess) break;
+            t.resident = c.resident;
+            t.tpw = c.tpw;
+            t.item_us = 0.0;
+            FusedPlan p;
+            // at most one workgroup per CU: the time of one item
+            e = fused_plan(p, {&t}, ncu, st);
+            double best = 1e30;
+            for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
+                e = hipEventRecord(e0, st);
+                if (e == hipSuccess) e = fused_launch(p, seed, 0, nullptr, steps, 1, st);
+                if (e == hipSuccess) e = hipEventRecord(e1, st);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                float ms = 0.0f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                best = std::min(best, 1e3 * (double)ms / steps);
+            }
+            fused_plan_free(p);
+            c.us = best;
+        }
+        (void)hipFree(t.d_R);
+        (void)hipFree(t.d_R0);
+        cands[b] = list;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return e;
+    // choose one shape per bucket: exhaustive over small products, otherwise
+    // each bucket's cheapest shape per tile
+    size_t combos = 1;
+    for (auto &l : cands) combos = std::min<size_t>(combos * std::max<size_t>(1, l.size()), 1 << 20);
+    std::vector<int> pick(bs.size(), 0), cur(bs.size(), 0);
+    auto evaluate = [&](const std::vector<int> &sel) {
+        std::vector<double> cost;
+        for (size_t b = 0; b < bs.size(); ++b) {
+            const Cand &c = cands[b][sel[b]];
+            const int ni = (bs[b]->ntiles + c.tpw - 1) / c.tpw;
+            cost.insert(cost.end(), (size_t)ni, c.us);
+        }
+        std::sort(cost.begin(), cost.end(), std::greater<double>());
+        return makespan(cost, ncu);
+    };
+    if (combos <= 4096) {
+        double best = 1e300;
+        for (size_t k = 0; k < combos; ++k) {
+            size_t r = k;
+            for (size_t b = 0; b < bs.size(); ++b) {
+                cur[b] = (int)(r % cands[b].size());
+                r /= cands[b].size();
+            }
+            const double m = evaluate(cur);
+            if (m < best) {
+                best = m;
+                pick = cur;
+            }
+        }
+    } else {
+        for (size_t b = 0; b < bs.size(); ++b) {
+            double best = 1e300;
+            for (size_t c = 0; c < cands[b].size(); ++c) {
+                const double per_tile = cands[b][c].us / cands[b][c].tpw;
+                if (per_tile < best) {
+                    best = per_tile;
+                    pick[b] = (int)c;
+                }
+            }
+        }
+    }
+    char line[256];
+    report.clear();
+    for (size_t b = 0; b < bs.size(); ++b) {
+        FusedBucket &f = *bs[b];
+        const Cand &c = cands[b][pick[b]];
+        f.resident = c.resident;
+        f.tpw = c.tpw;
+        f.item_us = c.us;
+        for (size_t k = 0; k < cands[b].size(); ++k) {
+            snprintf(line, sizeof line, "RT=%d %s tpw=%d: %.2f us/step%s\n", f.RT,
+                     cands[b][k].resident ? "resident" : "streamed", cands[b][k].tpw,
+                     cands[b][k].us, (int)k == pick[b] ? "  <- chosen" : "");
+            report += line;
+        }
+    }
+    return hipSuccess;
+}
+
+void fused_force_shape(FusedBucket &f, int table_mode, int tpw)
+{
+    if (table_mode == 1 && has_variant(f.RT, true) && fits_resident(f.RT, f.JC)) {
+        f.resident = 1;
+        f.item_us = 0.0;
+    } else if (table_mode == 2 && has_variant(f.RT, false)) {
+        f.resident = 0;
+        f.tpw = 4;
+        f.item_us = 0.0;
+    }
+    if (tpw >= 1 && tpw <= 4 && f.resident) {
+        f.tpw = tpw;
+        f.item_us = 0.0;
+    }
+}
+
+__global__ void set_step_kernel(int64_t *d_step, int64_t value, int64_t add)
+{
+    if (threadIdx.x == 0) *d_step = add ? *d_step + add : value;
+}
+
+hipError_t fused_set_step(int64_t *d_step, int64_t value, hipStream_t st)
+{
+    hipLaunchKernelGGL(set_step_kernel, dim3(1), dim3(64), 0, st, d_step, value, (int64_t)0);
+    return hipGetLastError();
+}
+
+hipError_t fused_advance_step(int64_t *d_step, int64_t n, hipStream_t st)
+{
+    hipLaunchKernelGGL(set_step_kernel, dim3(1), dim3(64), 0, st, d_step, (int64_t)0, n);
+    return hipGetLastError();
 }
 
 hipError_t fused_check_finite(const FusedBucket &f, int M, int n, int *flag, hipStream_t st)

@@ -1,0 +1,125 @@
+"""The fused launch: every length bucket in one kernel launch, tile shapes
+(forced or autotuned) and replayed HIP graphs of whole sampling blocks.
+
+Tile shapes only change which tiles share a workgroup and whether the
+transform tables stay in LDS; each tile runs the same instructions on the
+same data, so every shape must give bit-identical states.  A replayed graph
+runs the same kernels as the eager path, so it too must be bit-identical,
+replay after replay.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_1411_3487_amd import Context, inputs
+
+pytestmark = pytest.mark.gpu
+
+NU, TS = 0.35, 0.034
+B_FAC = 1.0 / (1.0 - 2.0 * NU)
+LENS = [64, 96, 128, 192, 256, 384, 512]
+DTAU = {64: 10.0, 96: 10.0, 128: 50.0, 192: 50.0, 256: 100.0, 384: 100.0, 512: 100.0}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    torch.cuda.set_device(0)
+    yield
+    torch.cuda.synchronize()
+
+
+def uneven(n, seed=2):
+    beads = inputs.mixed_lengths(n, LENS, seed=seed)
+    return beads, inputs.mixed_chains(beads, B_FAC, seed=seed)
+
+
+def run_modes(chains, prec, n_steps, **kw):
+    with Context(chains, seed=2, precision=prec) as ctx:
+        ctx.set_params(LENS, [DTAU[m] for m in LENS], T_star=TS, nu=NU, **kw)
+        ctx.step_modes(n_steps)
+        return ctx.modes(), ctx.tiling()
+
+
+def same(a, b):
+    return all(np.array_equal(x, y) for x, y in zip(a, b))
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_all_lengths_share_one_launch_and_shapes_agree(prec):
+    beads, chains = uneven(230)  # several tiles per length, ragged last tiles
+    ref, til = run_modes(chains, prec, 6)
+    print(prec, [(int(t["M"]), int(t["RT"]), int(t["JC"]), int(t["resident"]), int(t["tpw"]))
+                 for t in til])
+    assert [int(t["M"]) for t in til] == LENS
+    for mode, tpw in [("resident", 1), ("resident", 2), ("resident", 3), ("streamed", 0)]:
+        got, til2 = run_modes(chains, prec, 6, table_mode=mode, tiles_per_wg=tpw)
+        for t in til2:
+            if mode == "streamed" and t["RT"] >= 8:
+                assert t["resident"] == 0 and t["tpw"] == 4
+            if mode == "resident" and t["RT"] < 8:
+                assert t["resident"] == 1 and t["tpw"] == tpw
+        assert same(ref, got), (mode, tpw)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_autotuned_shapes_give_identical_states(prec):
+    beads, chains = uneven(300)
+    ref, _ = run_modes(chains, prec, 5)
+    with Context(chains, seed=2, precision=prec) as ctx:
+        ctx.set_params(LENS, [DTAU[m] for m in LENS], T_star=TS, nu=NU, autotune=True)
+        rep = ctx.tuning_report()
+        til = ctx.tiling()
+        ctx.step_modes(5)
+        got = ctx.modes()
+    print(rep)
+    assert rep.count("chosen") == len(LENS)
+    assert all(t["item_us"] > 0 for t in til)
+    assert same(ref, got)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_graph_replays_match_eager(prec):
+    """Sampling every 10 steps; calls that start off a block boundary and end
+    mid-block mix eager launches with replays.  After every call the state
+    and the accumulators of the graph context equal the eager context's."""
+    beads, chains = uneven(60)
+    ctxs = []
+    for graphs in (False, True):
+        c = Context(chains, seed=2, precision=prec)
+        c.set_params(LENS, [DTAU[m] for m in LENS], T_star=TS, nu=NU, sample_every=10,
+                     use_graphs=graphs)
+        ctxs.append(c)
+    try:
+        total = 0
+        for n in (7, 23, 40, 30, 5, 25):
+            for c in ctxs:
+                c.step_modes(n)
+            total += n
+            torch.cuda.synchronize()
+            eager, graph = [c.modes() for c in ctxs]
+            assert same(eager, graph), n
+            ae, ag = [c.accumulators() for c in ctxs]
+            for x, y in zip(ae, ag):
+                assert x["n_samples"] == y["n_samples"] == total // 10
+                for k in ("bond", "L2", "msd_cm"):
+                    assert x[k] == y[k], (n, k)
+                assert np.array_equal(x["modes"], y["modes"])
+            assert ctxs[0].step == ctxs[1].step
+    finally:
+        for c in ctxs:
+            c.close()
+
+
+def test_graph_replays_single_length_benchmark_shape():
+    """4096 x 256 bp, split BF16, observables every 100 steps."""
+    B, M = 4096, 256
+    pos = inputs.straight_chains(B, M, B_FAC, seed=1, random_orientation=True)
+    out = []
+    for graphs in (False, True):
+        with Context(pos, seed=1, precision="bf16x3") as c:
+            c.set_params([M], [100.0], T_star=TS, nu=NU, sample_every=100, use_graphs=graphs)
+            c.step_modes(300)
+            out.append((c.modes(), c.accumulators()[0]))
+    assert np.array_equal(out[0][0], out[1][0])
+    assert out[0][1]["L2"] == out[1][1]["L2"] and out[0][1]["n_samples"] == 3
