@@ -84,8 +84,15 @@ extern "C" {
 #define DM_CO_BOND2     15  /* mean squared bond length (1/N) sum_n |u_n|^2 */
 
 /* Accumulator block of one length bucket: DM_NACC_HEAD doubles, then the
-   sum over samples and chains of |R_p|^2 for p = 0..M-1. */
-#define DM_NACC_HEAD     8
+   sum over samples and chains of |R_p|^2 for p = 0..M-1, then
+   DM_NTUMBLE_BINS counts of tumbling times: bin k counts intervals tau
+   (in steps) with 2^k <= tau < 2^(k+1) (the last bin also everything
+   longer).  Tumbling (Sec. 7d, simple shear): the in-plane end-to-end
+   vector (L_x, L_y) is "along +x" once L_x > |(L_x, L_y)|/2 and "along -x"
+   once L_x < -|(L_x, L_y)|/2 (hysteresis: in between the previous state is
+   kept); each change between the two states at a sample is one tumble, and
+   a tumbling time is the interval between two tumbles of a chain. */
+#define DM_NACC_HEAD    13
 #define DM_ACC_M         0  /* beads per chain in this bucket */
 #define DM_ACC_NCHAINS   1
 #define DM_ACC_NSAMPLES  2  /* number of sampling events */
@@ -94,6 +101,12 @@ extern "C" {
 #define DM_ACC_L2        5  /* sum of DM_CO_L2 */
 #define DM_ACC_MSDCM     6  /* sum of |r_cm - r_cm at the last reset|^2 */
 #define DM_ACC_DMID2     7  /* sum of |r_mid - r_cm|^2 */
+#define DM_ACC_XSPAN     8  /* sum of DM_CO_XSPAN (extension along the flow) */
+#define DM_ACC_TUMBLES   9  /* number of tumbles */
+#define DM_ACC_TAU      10  /* sum of tumbling times (steps) */
+#define DM_ACC_TAU2     11  /* sum of squared tumbling times (steps^2) */
+#define DM_ACC_NTAU     12  /* number of tumbling times */
+#define DM_NTUMBLE_BINS 32
 
 /* dm_get_tiling(): DM_NTILING doubles per length bucket. */
 #define DM_NTILING       8

@@ -15,6 +15,7 @@ bead or mode index along the row); several chains are (B, 3, M).
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 
@@ -213,3 +214,40 @@ def chain_observables(pos) -> np.ndarray:
     for c in range(flat.shape[0]):
         lib.orc_chain_observables(flat.shape[-1], _ptr(flat[c]), _ptr(out[c]))
     return out
+
+
+TUMBLE_BINS = 32
+
+
+def tumbles(Lx, Ly, steps):
+    """Tumbles of one chain under simple shear (Sec. 7d) from its in-plane
+    end-to-end vector (Lx, Ly) sampled at the given steps.
+
+    The paper shows tumbling without defining it; the reading used here: the
+    chain points along +x once Lx > |(Lx, Ly)|/2 and along -x once
+    Lx < -|(Lx, Ly)|/2, and keeps its previous orientation in between
+    (hysteresis, so thermal jitter about the y axis is not counted).  Every
+    change of orientation is one tumble (half a turn); a tumbling time is the
+    number of steps between two consecutive tumbles.
+
+    Returns (number of tumbles, list of tumbling times in steps)."""
+    state, last, n, times = 0, None, 0, []
+    for lx, ly, k in zip(Lx, Ly, steps):
+        rho = math.sqrt(lx * lx + ly * ly)
+        new = 1 if lx > 0.5 * rho else (-1 if lx < -0.5 * rho else state)
+        if state != 0 and new != state:
+            n += 1
+            if last is not None:
+                times.append(k - last)
+            last = k
+        state = new
+    return n, times
+
+
+def tumble_histogram(times) -> np.ndarray:
+    """Counts of tumbling times in octaves: bin j holds 2^j <= tau < 2^(j+1)
+    steps (the last bin also everything longer)."""
+    h = np.zeros(TUMBLE_BINS)
+    for t in times:
+        h[min(TUMBLE_BINS - 1, int(math.floor(math.log2(t))))] += 1
+    return h

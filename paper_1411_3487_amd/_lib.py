@@ -31,10 +31,12 @@ DM_OBS_MODES = 2
 DM_OBS_ACCUM = 4
 DM_OBS_RESET = 8
 DM_NCHAIN_OBS = 16
-DM_NACC_HEAD = 8
+DM_NACC_HEAD = 13
+DM_NTUMBLE_BINS = 32
 CHAIN_OBS_NAMES = ["bond_mean", "L2", "Lx", "Ly", "Lz", "cmx", "cmy", "cmz",
                    "umx", "umy", "umz", "dmx", "dmy", "dmz", "xspan", "bond2_mean"]
-ACC_NAMES = ["M", "n_chains", "n_samples", "bond", "bond2", "L2", "msd_cm", "dmid2"]
+ACC_NAMES = ["M", "n_chains", "n_samples", "bond", "bond2", "L2", "msd_cm", "dmid2", "xspan",
+             "tumbles", "tau", "tau2", "n_tau"]
 DM_NTILING = 8
 TILING_NAMES = ["M", "n_chains", "RT", "JC", "resident", "tpw", "items", "item_us"]
 
@@ -211,15 +213,18 @@ class Context:
         return self.observables(DM_OBS_CHAIN).reshape(-1, DM_NCHAIN_OBS)
 
     def accumulators(self, reset=False) -> list:
-        """Per length bucket: dict of the head sums and 'modes' (sum |R_p|^2)."""
+        """Per length bucket: dict of the head sums, 'modes' (sum |R_p|^2) and
+        'tumble_hist' (counts of tumbling times in octaves of steps)."""
         flat = self.observables(DM_OBS_ACCUM | (DM_OBS_RESET if reset else 0))
         out, i = [], 0
         while i < flat.size:
             M = int(flat[i])
             d = dict(zip(ACC_NAMES, flat[i:i + DM_NACC_HEAD]))
-            d["modes"] = flat[i + DM_NACC_HEAD:i + DM_NACC_HEAD + M].copy()
+            j = i + DM_NACC_HEAD
+            d["modes"] = flat[j:j + M].copy()
+            d["tumble_hist"] = flat[j + M:j + M + DM_NTUMBLE_BINS].copy()
             out.append(d)
-            i += DM_NACC_HEAD + M
+            i = j + M + DM_NTUMBLE_BINS
         return out
 
     def _split(self, flat):

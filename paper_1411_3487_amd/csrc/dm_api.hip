@@ -38,8 +38,9 @@ struct Bucket {
     double *d_dH = nullptr;          // n*3*M coupling
     double *d_obs = nullptr;         // n*16
     double *d_m2 = nullptr;          // n*M
-    double *d_acc = nullptr;         // n*(8+M)
-    double *d_accsum = nullptr;      // 8+M
+    double *d_acc = nullptr;         // n*acc_width(M)
+    double *d_accsum = nullptr;      // acc_width(M)
+    double *d_tumble = nullptr;      // 2n: tumbling state, step of the last tumble + 1
     double *d_cm0 = nullptr;         // n*3
     dm::FusedBucket fused;           // reduced-precision state and tables
 };
@@ -114,7 +115,7 @@ void free_bucket(Bucket &b)
 {
     void *ptrs[] = {b.d_ids, b.d_off,  b.d_Ainv, b.d_Apos, b.d_Afwd, b.d_E,   b.d_C,
                     b.d_W,   b.d_R64, b.d_r,    b.d_F,    b.d_dH,   b.d_obs, b.d_m2,
-                    b.d_acc, b.d_accsum, b.d_cm0};
+                    b.d_acc, b.d_accsum, b.d_cm0, b.d_tumble};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     dm::fused_free(b.fused);
@@ -131,13 +132,18 @@ int bucket_positions(dm_ctx *ctx, Bucket &b, hipStream_t st)
     return DM_OK;
 }
 
-int observe(dm_ctx *ctx, int accumulate, hipStream_t st)
+// Observables of the current state; with accumulate != 0 also the sums and
+// the tumbling state, at the step held in ctx->d_step (set here unless the
+// call is being captured, where the block's own counter kernel keeps it).
+int observe(dm_ctx *ctx, int accumulate, hipStream_t st, bool captured = false)
 {
+    if (accumulate && !captured) DM_HIP(ctx, dm::fused_set_step(ctx->d_step, ctx->step, st));
     for (Bucket &b : ctx->buckets) {
         int rc = bucket_positions(ctx, b, st);
         if (rc) return rc;
-        DM_HIP(ctx, dm::launch_chain_obs(b.d_r, b.d_R64, b.d_obs, b.d_m2, b.d_acc, b.d_cm0, b.M,
-                                         b.n, accumulate, st));
+        DM_HIP(ctx, dm::launch_chain_obs(b.d_r, b.d_R64, b.d_obs, b.d_m2, b.d_acc, b.d_cm0,
+                                         b.d_tumble, b.d_tumble + b.n, ctx->d_step, b.M, b.n,
+                                         accumulate, st));
     }
     return DM_OK;
 }
@@ -163,7 +169,7 @@ int capture_block(dm_ctx *ctx, int steps)
     hipError_t e = dm::fused_launch(ctx->plan, ctx->seed, 0, ctx->d_step, steps, ctx->nonlinear,
                                     ctx->cap_stream);
     if (e == hipSuccess) e = dm::fused_advance_step(ctx->d_step, steps, ctx->cap_stream);
-    int rc = e == hipSuccess ? observe(ctx, 1, ctx->cap_stream) : DM_OK;
+    int rc = e == hipSuccess ? observe(ctx, 1, ctx->cap_stream, true) : DM_OK;
     hipGraph_t g = nullptr;
     const hipError_t ec = hipStreamEndCapture(ctx->cap_stream, &g);
     if (e != hipSuccess || rc != DM_OK || ec != hipSuccess) {
@@ -303,8 +309,9 @@ int dm_init_chains(dm_ctx **out, int32_t n_chains, const int32_t *beads, const d
             (rc = dalloc(ctx, &b.d_F, S)) || (rc = dalloc(ctx, &b.d_dH, S)) ||
             (rc = dalloc(ctx, &b.d_obs, (size_t)16 * b.n)) ||
             (rc = dalloc(ctx, &b.d_m2, (size_t)b.M * b.n)) ||
-            (rc = dalloc(ctx, &b.d_acc, (size_t)(8 + b.M) * b.n)) ||
-            (rc = dalloc(ctx, &b.d_accsum, (size_t)(8 + b.M))) ||
+            (rc = dalloc(ctx, &b.d_acc, (size_t)dm::acc_width(b.M) * b.n)) ||
+            (rc = dalloc(ctx, &b.d_accsum, (size_t)dm::acc_width(b.M))) ||
+            (rc = dalloc(ctx, &b.d_tumble, (size_t)2 * b.n)) ||
             (rc = dalloc(ctx, &b.d_cm0, (size_t)3 * b.n)))
             return bail(rc);
         dm::rouse_matrix(b.M, phi);
@@ -336,7 +343,10 @@ int dm_init_chains(dm_ctx **out, int32_t n_chains, const int32_t *beads, const d
         up(b.d_r, pos.data(), sizeof(double) * S);
         up(b.d_cm0, cm0.data(), sizeof(double) * 3 * b.n);
         if (e == hipSuccess)
-            e = hipMemsetAsync(b.d_acc, 0, sizeof(double) * (8 + b.M) * b.n, ctx->stream);
+            e = hipMemsetAsync(b.d_acc, 0, sizeof(double) * dm::acc_width(b.M) * b.n,
+                               ctx->stream);
+        if (e == hipSuccess)
+            e = hipMemsetAsync(b.d_tumble, 0, sizeof(double) * 2 * b.n, ctx->stream);
         if (e == hipSuccess)
             e = dm::launch_gemm_f64(b.d_Afwd, b.d_r, b.d_R64, b.M, 3 * b.n, ctx->stream);
         if (e == hipSuccess && fused_precision(precision)) {
@@ -517,7 +527,7 @@ int dm_observables_size(const dm_ctx *ctx, int32_t which, size_t *len)
     if (which & DM_OBS_CHAIN) n += (size_t)DM_NCHAIN_OBS * ctx->nchains;
     if (which & DM_OBS_MODES) n += ctx->total / 3;
     if (which & DM_OBS_ACCUM)
-        for (const Bucket &b : ctx->buckets) n += DM_NACC_HEAD + b.M;
+        for (const Bucket &b : ctx->buckets) n += dm::acc_width(b.M);
     *len = n;
     return DM_OK;
 }
@@ -559,7 +569,7 @@ int dm_observables(dm_ctx *ctx, int32_t which, double *out_host, size_t out_len)
     }
     if (which & DM_OBS_ACCUM) {
         for (Bucket &b : ctx->buckets) {
-            const int w = 8 + b.M;
+            const int w = dm::acc_width(b.M);
             DM_HIP(ctx, dm::launch_reduce_chains(b.d_acc, b.d_accsum, w, b.n, ctx->stream));
             DM_HIP(ctx, hipMemcpyAsync(o, b.d_accsum, sizeof(double) * w, hipMemcpyDeviceToHost,
                                        ctx->stream));
@@ -575,8 +585,10 @@ int dm_observables(dm_ctx *ctx, int32_t which, double *out_host, size_t out_len)
         int rc = observe(ctx, 0, ctx->stream);
         if (rc) return rc;
         for (Bucket &b : ctx->buckets) {
-            DM_HIP(ctx, hipMemsetAsync(b.d_acc, 0, sizeof(double) * (8 + b.M) * b.n,
+            DM_HIP(ctx, hipMemsetAsync(b.d_acc, 0, sizeof(double) * dm::acc_width(b.M) * b.n,
                                        ctx->stream));
+            // tumbling times restart; the orientation state is kept
+            DM_HIP(ctx, hipMemsetAsync(b.d_tumble + b.n, 0, sizeof(double) * b.n, ctx->stream));
             DM_HIP(ctx, hipMemcpy2DAsync(b.d_cm0, 3 * sizeof(double), b.d_obs + DM_CO_CM,
                                          16 * sizeof(double), 3 * sizeof(double), b.n,
                                          hipMemcpyDeviceToDevice, ctx->stream));
@@ -626,20 +638,22 @@ int dm_get_modes(dm_ctx *ctx, double *dst)
 }
 
 // State blob: header, then per bucket the FP64 modes (n*3*M), the centre of
-// mass reference (n*3) and the per-chain accumulators (n*(8+M)).
+// mass reference (n*3), the per-chain accumulators (n*acc_width(M)) and the
+// tumbling state (2n).
 struct StateHeader {
     uint64_t magic;
     int64_t step;
     int32_t nchains, precision, nbuckets, pad;
 };
-static const uint64_t kStateMagic = 0x314d4f444d4e4144ull;  // "DANMDOM1"
+static const uint64_t kStateMagic = 0x324d4f444d4e4144ull;  // "DANMDOM2"
 
 static size_t state_size(const dm_ctx *ctx)
 {
     size_t s = sizeof(StateHeader);
     for (const Bucket &b : ctx->buckets)
         s += sizeof(int32_t) * 2 + sizeof(double) * ((size_t)3 * b.M * b.n + 3 * (size_t)b.n +
-                                                     (size_t)(8 + b.M) * b.n);
+                                                     (size_t)dm::acc_width(b.M) * b.n +
+                                                     2 * (size_t)b.n);
     return s;
 }
 
@@ -664,11 +678,14 @@ int dm_save_state(dm_ctx *ctx, void *buf, size_t *len)
         if (fused_precision(ctx->precision))
             DM_HIP(ctx, dm::fused_unpack_modes(b.fused, b.d_R64, b.M, b.n, ctx->stream));
         const size_t s1 = sizeof(double) * 3 * b.M * b.n, s2 = sizeof(double) * 3 * b.n,
-                     s3 = sizeof(double) * (8 + b.M) * b.n;
+                     s3 = sizeof(double) * dm::acc_width(b.M) * b.n,
+                     s4 = sizeof(double) * 2 * b.n;
         DM_HIP(ctx, hipMemcpyAsync(p, b.d_R64, s1, hipMemcpyDeviceToHost, ctx->stream));
         DM_HIP(ctx, hipMemcpyAsync(p + s1, b.d_cm0, s2, hipMemcpyDeviceToHost, ctx->stream));
         DM_HIP(ctx, hipMemcpyAsync(p + s1 + s2, b.d_acc, s3, hipMemcpyDeviceToHost, ctx->stream));
-        p += s1 + s2 + s3;
+        DM_HIP(ctx, hipMemcpyAsync(p + s1 + s2 + s3, b.d_tumble, s4, hipMemcpyDeviceToHost,
+                                   ctx->stream));
+        p += s1 + s2 + s3 + s4;
     }
     DM_HIP(ctx, hipStreamSynchronize(ctx->stream));
     *len = need;
@@ -693,18 +710,21 @@ int dm_load_state(dm_ctx *ctx, const void *buf, size_t len)
         if (mn[0] != b.M || mn[1] != b.n)
             return fail(ctx, DM_EINVAL, "state blob bucket mismatch");
         q += sizeof mn + sizeof(double) * ((size_t)3 * b.M * b.n + 3 * (size_t)b.n +
-                                           (size_t)(8 + b.M) * b.n);
+                                           (size_t)dm::acc_width(b.M) * b.n + 2 * (size_t)b.n);
     }
     for (Bucket &b : ctx->buckets) {
         p += 2 * sizeof(int32_t);
         const size_t s1 = sizeof(double) * 3 * b.M * b.n, s2 = sizeof(double) * 3 * b.n,
-                     s3 = sizeof(double) * (8 + b.M) * b.n;
+                     s3 = sizeof(double) * dm::acc_width(b.M) * b.n,
+                     s4 = sizeof(double) * 2 * b.n;
         DM_HIP(ctx, hipMemcpyAsync(b.d_R64, p, s1, hipMemcpyHostToDevice, ctx->stream));
         DM_HIP(ctx, hipMemcpyAsync(b.d_cm0, p + s1, s2, hipMemcpyHostToDevice, ctx->stream));
         DM_HIP(ctx, hipMemcpyAsync(b.d_acc, p + s1 + s2, s3, hipMemcpyHostToDevice, ctx->stream));
+        DM_HIP(ctx, hipMemcpyAsync(b.d_tumble, p + s1 + s2 + s3, s4, hipMemcpyHostToDevice,
+                                   ctx->stream));
         if (fused_precision(ctx->precision))
             DM_HIP(ctx, dm::fused_pack_modes(b.fused, b.d_R64, b.M, b.n, ctx->stream));
-        p += s1 + s2 + s3;
+        p += s1 + s2 + s3 + s4;
     }
     DM_HIP(ctx, hipStreamSynchronize(ctx->stream));
     ctx->step = h.step;

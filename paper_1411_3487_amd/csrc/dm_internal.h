@@ -3,7 +3,12 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/dnamodes.h"
+
 namespace dm {
+
+// Doubles of one chain's accumulators: head, |R_p|^2 sums, tumbling bins.
+__host__ __device__ inline int acc_width(int M) { return DM_NACC_HEAD + M + DM_NTUMBLE_BINS; }
 
 // Plain-form (FP64) kernels, dm_plain.hip.  Every launcher only enqueues on
 // `st` and returns the launch status.
@@ -35,10 +40,14 @@ hipError_t launch_euler_f64(double *pos, const int32_t *ids, int M, int nch,
 
 // Per-chain observables from positions and modes; writes obs[c*16 + .] and
 // m2[c*M + p] = |R_p|^2, and adds into the per-chain accumulators
-// acc[c*(8+M) + .] when accumulate != 0.
+// acc[c*acc_width(M) + .] when accumulate != 0, advancing the tumbling state
+// (tstate[c] = -1, 0, +1; tlast[c] = step of the last tumble + 1, or 0) with
+// the current step *step_dev.
 hipError_t launch_chain_obs(const double *pos, const double *R, double *obs,
-                            double *m2, double *acc, const double *cm0, int M,
-                            int nch, int accumulate, hipStream_t st);
+                            double *m2, double *acc, const double *cm0,
+                            double *tstate, double *tlast,
+                            const int64_t *step_dev, int M, int nch,
+                            int accumulate, hipStream_t st);
 
 // out[j] = sum_c acc[c*width + j], summed over chains in order.
 hipError_t launch_reduce_chains(const double *acc, double *out, int width,

@@ -263,6 +263,9 @@ __global__ __launch_bounds__(64) void chain_obs_kernel(const double *__restrict_
                                                        double *__restrict__ m2,
                                                        double *__restrict__ acc,
                                                        const double *__restrict__ cm0,
+                                                       double *__restrict__ tstate,
+                                                       double *__restrict__ tlast,
+                                                       const int64_t *__restrict__ step_dev,
                                                        int M, int accumulate)
 {
     const int c = blockIdx.x, lane = threadIdx.x;
@@ -291,11 +294,11 @@ __global__ __launch_bounds__(64) void chain_obs_kernel(const double *__restrict_
     xmin = wave_min(xmin);
     xmax = wave_max(xmax);
     const double *Rc = R + (size_t)c * 3 * M;
-    double *accc = acc + (size_t)c * (8 + M);
+    double *accc = acc + (size_t)c * acc_width(M);
     for (int p = lane; p < M; p += 64) {
         const double v = Rc[p] * Rc[p] + Rc[M + p] * Rc[M + p] + Rc[2 * M + p] * Rc[2 * M + p];
         m2[(size_t)c * M + p] = v;
-        if (accumulate) accc[8 + p] += v;
+        if (accumulate) accc[DM_NACC_HEAD + p] += v;
     }
     if (lane == 0) {
         double o[16];
@@ -320,12 +323,31 @@ __global__ __launch_bounds__(64) void chain_obs_kernel(const double *__restrict_
         if (accumulate) {
             const double dx = o[5] - cm0[3 * c], dy = o[6] - cm0[3 * c + 1],
                          dz = o[7] - cm0[3 * c + 2];
-            accc[2] += 1.0;
-            accc[3] += o[0];
-            accc[4] += o[15];
-            accc[5] += o[1];
-            accc[6] += dx * dx + dy * dy + dz * dz;
-            accc[7] += o[11] * o[11] + o[12] * o[12] + o[13] * o[13];
+            accc[DM_ACC_NSAMPLES] += 1.0;
+            accc[DM_ACC_BOND] += o[0];
+            accc[DM_ACC_BOND2] += o[15];
+            accc[DM_ACC_L2] += o[1];
+            accc[DM_ACC_MSDCM] += dx * dx + dy * dy + dz * dz;
+            accc[DM_ACC_DMID2] += o[11] * o[11] + o[12] * o[12] + o[13] * o[13];
+            accc[DM_ACC_XSPAN] += o[14];
+            // tumbling in the flow plane, with hysteresis (see dnamodes.h)
+            const double rho = sqrt(Lx * Lx + Ly * Ly);
+            const double s0 = tstate[c];
+            const double s1 = Lx > 0.5 * rho ? 1.0 : (Lx < -0.5 * rho ? -1.0 : s0);
+            if (s0 != 0.0 && s1 != s0) {
+                const double k = (double)*step_dev;
+                accc[DM_ACC_TUMBLES] += 1.0;
+                if (tlast[c] > 0.0) {
+                    const double tau = k - (tlast[c] - 1.0);
+                    accc[DM_ACC_TAU] += tau;
+                    accc[DM_ACC_TAU2] += tau * tau;
+                    accc[DM_ACC_NTAU] += 1.0;
+                    const int bin = min(DM_NTUMBLE_BINS - 1, max(0, ilogb(tau)));
+                    accc[DM_NACC_HEAD + M + bin] += 1.0;
+                }
+                tlast[c] = k + 1.0;
+            }
+            tstate[c] = s1;
         }
     }
 }
@@ -410,12 +432,13 @@ hipError_t launch_euler_f64(double *pos, const int32_t *ids, int M, int nch, dou
 }
 
 hipError_t launch_chain_obs(const double *pos, const double *R, double *obs, double *m2,
-                            double *acc, const double *cm0, int M, int nch, int accumulate,
+                            double *acc, const double *cm0, double *tstate, double *tlast,
+                            const int64_t *step_dev, int M, int nch, int accumulate,
                             hipStream_t st)
 {
     if (nch == 0) return hipSuccess;
     hipLaunchKernelGGL(chain_obs_kernel, dim3(nch), dim3(64), 0, st, pos, R, obs, m2, acc, cm0,
-                       M, accumulate);
+                       tstate, tlast, step_dev, M, accumulate);
     return hipGetLastError();
 }
 

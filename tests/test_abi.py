@@ -34,7 +34,7 @@ def test_header_constants_match_binding():
     for name in ["DM_OK", "DM_EINVAL", "DM_ENOMEM", "DM_EHIP", "DM_ENONFINITE", "DM_ESTATE",
                  "DM_FP64", "DM_FP32", "DM_BF16X3", "DM_OBS_CHAIN", "DM_OBS_MODES",
                  "DM_OBS_ACCUM", "DM_OBS_RESET", "DM_NCHAIN_OBS", "DM_NACC_HEAD",
-                 "DM_NTILING"]:
+                 "DM_NTILING", "DM_NTUMBLE_BINS"]:
         assert int(consts[name]) == getattr(_lib, name), name
     assert len(_lib.CHAIN_OBS_NAMES) == _lib.DM_NCHAIN_OBS
     assert len(_lib.ACC_NAMES) == _lib.DM_NACC_HEAD

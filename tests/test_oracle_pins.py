@@ -489,3 +489,37 @@ def test_chain_observables_of_a_straight_chain():
     mid = (M - 1) // 2
     assert np.allclose(o[11:14], e * s * (mid - (M - 1) / 2))
     assert names["xspan"] == pytest.approx(0.6 * (M - 1) * s)
+
+
+# ---------------------------------------------------------------- tumbling
+def test_tumbles_of_a_uniform_rotation():
+    """(L_x, L_y) turning at one revolution per 1000 steps, sampled every
+    step from angle 0: the orientation first flips when the angle passes
+    120 degrees (step 333.3, seen at 334), then every half turn; 10 tumbles
+    in 5000 steps, 9 tumbling times of exactly 500 steps, either sense."""
+    k = np.arange(1, 5001)
+    for sense in (1.0, -1.0):
+        th = sense * 2 * np.pi * k / 1000.0
+        n, times = oracle.tumbles(np.cos(th), np.sin(th), k)
+        assert n == 10
+        assert times == [500] * 9
+
+
+def test_tumbles_need_the_hysteresis_band_to_be_crossed():
+    k = np.arange(200)
+    # never within 60 degrees of the x axis: no orientation, no tumble
+    n, t = oracle.tumbles(0.45 * np.cos(k / 3.0), np.ones(200), k)
+    assert n == 0 and t == []
+    # aligned, then jitter about the y axis, then reversed: one tumble
+    lx = np.concatenate([[1.0], 0.3 * (-1.0) ** k[:50], [-1.0]])
+    ly = np.concatenate([[0.0], np.ones(50), [0.0]])
+    n, t = oracle.tumbles(lx, ly, np.arange(52))
+    assert n == 1 and t == []
+
+
+def test_tumble_histogram_octaves():
+    h = oracle.tumble_histogram([1, 2, 3, 4, 7, 8, 1000, 2 ** 40])
+    want = np.zeros(oracle.TUMBLE_BINS)
+    for b in (0, 1, 1, 2, 2, 3, 9, oracle.TUMBLE_BINS - 1):
+        want[b] += 1
+    assert np.array_equal(h, want)
