@@ -26,6 +26,11 @@ PEAKS = {"bf16x3": 2.5e15, "fp32": 157.3e12, "fp64": 78.6e12}  # dense MFMA, MI3
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--workload", default="modes", choices=["modes", "uneven", "shear"],
+                    help="modes: 4096 x 256 bp (the headline line); uneven: 8192 chains of "
+                         "64..512 bp in one launch; shear: 2048 x 256 bp under simple shear "
+                         "at Wi = 1, 10, 100 (tumbling and extension, FP32 vs FP64)")
+    ap.add_argument("--shear-steps", type=int, default=1000000)
     ap.add_argument("--steps", type=int, default=20000)
     ap.add_argument("--warmup", type=int, default=1000)
     ap.add_argument("--precision", default="bf16x3", choices=["bf16x3", "fp32"])
@@ -102,8 +107,120 @@ def cpu_baseline(args, pos, nu, ts):
                       f"steps (FP64 plain C, OpenMP over chains), {dt:.1f} s"}
 
 
+LENGTHS = [64, 96, 128, 192, 256, 384, 512]
+DTAU_OF = {64: 10.0, 96: 10.0, 128: 50.0, 192: 50.0, 256: 100.0, 384: 100.0, 512: 100.0}
+
+
+def uneven_workload(args):
+    """8192 chains with lengths uniform over LENGTHS (seed 2), each at its
+    length's time step, advanced in one fused launch per sampling block."""
+    import numpy as np
+    import torch
+    from paper_1411_3487_amd import Context, inputs, NU_DSDNA, T_STAR_DSDNA
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    b = 1.0 / (1.0 - 2.0 * NU_DSDNA)
+    B = 8192
+    beads = inputs.mixed_lengths(B, LENGTHS, seed=2)
+    chains = inputs.mixed_chains(beads, b, seed=2)
+    steps = args.steps if args.steps != 20000 else 4000
+    dts = [DTAU_OF[m] for m in LENGTHS]
+    ctx = Context(chains, seed=2, precision=args.precision, stream=stream)
+    ctx.set_params(LENGTHS, dts, T_star=T_STAR_DSDNA, nu=NU_DSDNA,
+                   sample_every=args.sample_every, use_graphs=not args.no_graphs,
+                   autotune=not args.no_autotune)
+    tiling, report = ctx.tiling(), ctx.tuning_report()
+    ctx.step_modes(min(args.warmup, 500))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.step_modes(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    finite = bool(np.all(np.isfinite(ctx.chain_observables())))
+    ctx.close()
+    c64 = Context(chains, seed=2, precision="fp64", stream=stream)
+    c64.set_params(LENGTHS, dts, T_star=T_STAR_DSDNA, nu=NU_DSDNA, sample_every=args.sample_every)
+    c64.step_modes(10)
+    t64 = time_steps(c64, torch, 200, stream)
+    c64.close()
+    rate = B * steps / wall
+    out = {
+        "metric": "chain-steps/s, uneven ensemble (one launch for all lengths)",
+        "value": rate, "unit": "chain-steps/s", "n_gpus": 1, "steps": steps,
+        "ms_per_step": wall / steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": {"bf16x3": "bf16x3-f32acc", "fp32": "f32"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": f"{B} chains, lengths uniform over {LENGTHS} bp (seed 2), "
+                               f"dtau {dts}, observables every {args.sample_every} steps",
+                   "graphs": not args.no_graphs, "autotune": not args.no_autotune},
+        "bead_steps_per_s": rate * float(np.mean(beads)),
+        "fp64_plain_chain_steps_per_s": B * 200 / t64,
+        "speedup_vs_fp64_plain": rate / (B * 200 / t64),
+        "state_finite": finite,
+        "tiling": [{k: (float(v) if k == "item_us" else int(v)) for k, v in t.items()}
+                   for t in tiling],
+        "tuning_report": report.strip().splitlines(),
+    }
+    print(json.dumps(out))
+
+
+def shear_workload(args):
+    """2048 chains of 256 bp under simple shear at Wi = 1, 10, 100 relative
+    to the slowest mode (gamma_dot = Wi zeta_1), dtau = 100: tumbling times
+    and mean extension of the reduced-precision path against FP64 on the
+    GPU, same initial state and Philox streams."""
+    import numpy as np
+    import torch
+    from paper_1411_3487_amd import Context, inputs, NU_DSDNA, T_STAR_DSDNA
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    b = 1.0 / (1.0 - 2.0 * NU_DSDNA)
+    B, M, dtau, se = 2048, 256, 100.0, 1000
+    z1 = 16 * NU_DSDNA * np.sin(np.pi / (2 * M)) ** 4
+    pos = inputs.straight_chains(B, M, b, seed=1, random_orientation=True)
+    prec = args.precision if args.precision != "bf16x3" else "fp32"
+    res = []
+    for wi in (1.0, 10.0, 100.0):
+        row = {"Wi": wi, "gamma_dot": wi * z1}
+        for p in (prec, "fp64"):
+            ctx = Context(pos, seed=7, precision=p, stream=stream)
+            ctx.set_params([M], [dtau], T_star=T_STAR_DSDNA, nu=NU_DSDNA, gamma_dot=wi * z1,
+                           sample_every=se, use_graphs=p != "fp64")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            left = args.shear_steps
+            while left > 0:  # progress lines for long runs
+                n = min(left, 100000)
+                ctx.step_modes(n)
+                left -= n
+                torch.cuda.synchronize()
+                print(f"# Wi={wi:g} {p}: {args.shear_steps - left} steps", file=sys.stderr,
+                      flush=True)
+            wall = time.perf_counter() - t0
+            a = ctx.accumulators()[0]
+            ctx.close()
+            ns = a["n_samples"]
+            row[p] = {
+                "chain_steps_per_s": B * args.shear_steps / wall,
+                "mean_extension": a["xspan"] / ns / B / ((M - 1) * b),
+                "L2_over_contour2": a["L2"] / ns / B / ((M - 1) * b) ** 2,
+                "tumbles": a["tumbles"],
+                "tumbling_times": a["n_tau"],
+                "mean_tumbling_time_tau": (a["tau"] / a["n_tau"] * dtau) if a["n_tau"] else None,
+                "tumble_hist_octaves_of_steps": [int(x) for x in a["tumble_hist"]],
+            }
+        r, f = row[prec], row["fp64"]
+        row["extension_rel_diff"] = r["mean_extension"] / f["mean_extension"] - 1
+        res.append(row)
+    print(json.dumps({"workload": f"shear: {B} chains x {M} bp, dtau = {dtau:g}, "
+                                  f"{args.shear_steps} steps, samples every {se}",
+                      "precision": prec, "results": res}))
+
+
 def main():
     args = parse()
+    if args.workload != "modes" and args.gpus == 1:
+        return uneven_workload(args) if args.workload == "uneven" else shear_workload(args)
     if args.copy_calibration:
         import torch
         n = args.copy_calibration * (1 << 20) // 4

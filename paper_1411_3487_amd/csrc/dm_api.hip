@@ -139,6 +139,12 @@ int observe(dm_ctx *ctx, int accumulate, hipStream_t st, bool captured = false)
 {
     if (accumulate && !captured) DM_HIP(ctx, dm::fused_set_step(ctx->d_step, ctx->step, st));
     for (Bucket &b : ctx->buckets) {
+        if (fused_precision(ctx->precision)) {
+            DM_HIP(ctx, dm::fused_observe(b.fused, b.M, b.d_obs, b.d_m2, b.d_acc, b.d_cm0,
+                                          b.d_tumble, b.d_tumble + b.n, ctx->d_step, accumulate,
+                                          st));
+            continue;
+        }
         int rc = bucket_positions(ctx, b, st);
         if (rc) return rc;
         DM_HIP(ctx, dm::launch_chain_obs(b.d_r, b.d_R64, b.d_obs, b.d_m2, b.d_acc, b.d_cm0,

@@ -20,6 +20,7 @@ struct FusedBucket {
     double *d_R0 = nullptr;  // centre-of-mass mode, ntiles * 16 doubles
     float *d_coef = nullptr; // per-slot update coefficients (see dm_fused.hip)
     double *d_sig = nullptr; // sigma_p of the even modes, by half-mode slot
+    float *d_P = nullptr;    // FP32 position tables of the observables
     int JC = 0;              // coupling row tiles with non-negligible C_p
     int resident = 0;        // tables held in LDS for the whole launch
     int tpw = 4;             // tiles per workgroup (1..4; 4 when streamed)
@@ -66,6 +67,12 @@ void fused_force_shape(FusedBucket &f, int table_mode, int tpw);
 // Device step counter of replayed graphs: *d_step = value, *d_step += n.
 hipError_t fused_set_step(int64_t *d_step, int64_t value, hipStream_t st);
 hipError_t fused_advance_step(int64_t *d_step, int64_t n, hipStream_t st);
+// Per-chain observables, |R_p|^2 and (accumulate != 0) the FP64 accumulators
+// and tumbling state of the bucket, in the layout of launch_chain_obs, from
+// the fused state directly (positions in FP32 MFMA, sums in FP64).
+hipError_t fused_observe(const FusedBucket &f, int M, double *obs, double *m2, double *acc,
+                         const double *cm0, double *tstate, double *tlast,
+                         const int64_t *d_step, int accumulate, hipStream_t st);
 hipError_t fused_check_finite(const FusedBucket &f, int M, int n, int *flag, hipStream_t st);
 
 }  // namespace dm

@@ -51,6 +51,7 @@
 #include <vector>
 
 #include "dm_fused.h"
+#include "dm_internal.h"
 #include "dm_rng.h"
 
 namespace dm {
@@ -552,6 +553,173 @@ __device__ __forceinline__ size_t state_slot(int j, int alpha, int p, int RT)
     return (((size_t)T * 2 + set) * RT + t) * 256 + (size_t)lane * 4 + (rho % 4);
 }
 
+// Observables of the fused state, one wavefront per tile.  Positions
+// relative to the centre of mass, r_n - r_cm = sum_{p >= 1} phi_{n,p} R_p
+// (Eq. c1; the internal modes sum to zero over the beads), in the mirror
+// halves of Sec. 5a: for beads n < H
+//   O_n = sum_{p odd} phi_{n,p} R_p,  E_n = sum_{p even} phi_{n,p} R_p,
+//   r_n = E_n + O_n,  r_{M-1-n} = E_n - O_n,
+// as FP32 MFMA products with the tables P (odd: phi_{n,2j+1}; even:
+// phi_{n,2j+2} / sigma_{2j+2}, undoing the scaling of the stored even
+// amplitudes), fragment (I, t, kind) holding rows 16 I + l%16 and K slots
+// 16 t + 4 (l/16) + r.  The positions go to LDS; then 8 lanes per chain
+// reduce bond lengths, end-to-end vector and extent in FP64, and the
+// per-chain outputs and accumulators follow the FP64 path's layout.
+struct ObsArgs {
+    const float *R;
+    const double *R0;
+    const float *P;
+    const double *sig;
+    double *obs, *m2, *acc;
+    const double *cm0;
+    double *tstate, *tlast;
+    const int64_t *step;
+    int M, n, accumulate;
+};
+
+template <int RT>
+__global__ __launch_bounds__(64) void fused_obs_kernel(ObsArgs a)
+{
+    extern __shared__ float pos[];  // [16][M]
+    const int M = a.M, H = M / 2, tile = blockIdx.x;
+    const int lane = threadIdx.x, col = lane & 15, g = lane >> 4;
+    const int cl = col / 3, alpha = col - 3 * cl;
+    const int nvalid = min(kChainsPerTile, a.n - kChainsPerTile * tile);
+    f32x4 Ro[RT], Re[RT];
+    const f32x4 *Rt = reinterpret_cast<const f32x4 *>(a.R) + (size_t)tile * 2 * RT * 64;
+#pragma unroll
+    for (int t = 0; t < RT; ++t) {
+        Ro[t] = Rt[(0 * RT + t) * 64 + lane];
+        Re[t] = Rt[(1 * RT + t) * 64 + lane];
+    }
+    const f32x4 *P = reinterpret_cast<const f32x4 *>(a.P);
+    for (int I = 0; I < RT; ++I) {
+        f32x4 o = f32x4{0.f, 0.f, 0.f, 0.f}, e = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int t = 0; t < RT; ++t) {
+            const f32x4 po = P[((I * RT + t) * 2) * 64 + lane];
+            const f32x4 pe = P[((I * RT + t) * 2 + 1) * 64 + lane];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                o = mfma_f32(po[r], Ro[t][r], o);
+                e = mfma_f32(pe[r], Re[t][r], e);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int nb = 16 * I + 4 * g + r;
+            if (nb < H) {
+                pos[col * M + nb] = e[r] + o[r];
+                pos[col * M + M - 1 - nb] = e[r] - o[r];
+            }
+        }
+    }
+    // |R_p|^2 of p >= 1, summed over the chain's three component lanes
+    const int W = acc_width(M);
+    for (int t = 0; t < RT; ++t) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int j = 16 * t + 4 * g + r;
+            const float vo = Ro[t][r];
+            const float ve = j < H - 1 ? (float)((double)Re[t][r] / a.sig[j]) : 0.0f;
+            const float so = comp_sum(vo * vo, alpha), se = comp_sum(ve * ve, alpha);
+            if (alpha == 0 && col < 15 && cl < nvalid) {
+                const size_t c = (size_t)kChainsPerTile * tile + cl;
+                const int po = 2 * j + 1, pe = 2 * j + 2;
+                if (po < M) {
+                    a.m2[c * M + po] = so;
+                    if (a.accumulate) a.acc[c * W + DM_NACC_HEAD + po] += so;
+                }
+                if (pe < M) {
+                    a.m2[c * M + pe] = se;
+                    if (a.accumulate) a.acc[c * W + DM_NACC_HEAD + pe] += se;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    // 8 lanes per chain: bond lengths and the x extent
+    const int c8 = lane >> 3, part = lane & 7;
+    const bool cv = c8 < nvalid;
+    const float *px = pos + 3 * (cv ? c8 : 0) * M, *py = px + M, *pz = py + M;
+    double ls = 0.0, l2s = 0.0, xmin = 1e300, xmax = -1e300;
+    if (cv) {
+        for (int nb = part; nb < M; nb += 8) {
+            const double x = px[nb];
+            xmin = fmin(xmin, x);
+            xmax = fmax(xmax, x);
+            if (nb >= 1) {
+                const double ux = x - px[nb - 1], uy = (double)py[nb] - py[nb - 1],
+                             uz = (double)pz[nb] - pz[nb - 1];
+                const double q = ux * ux + uy * uy + uz * uz;
+                ls += sqrt(q);
+                l2s += q;
+            }
+        }
+    }
+#pragma unroll
+    for (int off = 1; off < 8; off <<= 1) {
+        ls += __shfl_xor(ls, off, 64);
+        l2s += __shfl_xor(l2s, off, 64);
+        xmin = fmin(xmin, __shfl_xor(xmin, off, 64));
+        xmax = fmax(xmax, __shfl_xor(xmax, off, 64));
+    }
+    if (!cv || part != 0) return;
+    const size_t c = (size_t)kChainsPerTile * tile + c8;
+    const double *r0 = a.R0 + (size_t)tile * 16 + 3 * c8;
+    const double rs = 1.0 / sqrt((double)M);
+    double o[DM_NCHAIN_OBS];
+    o[DM_CO_BOND] = ls / (M - 1);
+    const double Lx = (double)px[M - 1] - px[0], Ly = (double)py[M - 1] - py[0],
+                 Lz = (double)pz[M - 1] - pz[0];
+    o[DM_CO_L2] = Lx * Lx + Ly * Ly + Lz * Lz;
+    o[DM_CO_LX] = Lx;
+    o[DM_CO_LX + 1] = Ly;
+    o[DM_CO_LX + 2] = Lz;
+    const int m = M / 2, mid = (M - 1) / 2;
+    const float *pc[3] = {px, py, pz};
+    for (int k = 0; k < 3; ++k) {
+        o[DM_CO_CM + k] = r0[k] * rs;
+        o[DM_CO_UMID + k] = (double)pc[k][m] - pc[k][m - 1];
+        o[DM_CO_DMID + k] = pc[k][mid];
+    }
+    o[DM_CO_XSPAN] = xmax - xmin;
+    o[DM_CO_BOND2] = l2s / (M - 1);
+    for (int k = 0; k < DM_NCHAIN_OBS; ++k) a.obs[c * DM_NCHAIN_OBS + k] = o[k];
+    const double m20 = r0[0] * r0[0] + r0[1] * r0[1] + r0[2] * r0[2];
+    a.m2[c * M] = m20;
+    if (!a.accumulate) return;
+    double *ac = a.acc + c * W;
+    const double dx = o[DM_CO_CM] - a.cm0[3 * c], dy = o[DM_CO_CM + 1] - a.cm0[3 * c + 1],
+                 dz = o[DM_CO_CM + 2] - a.cm0[3 * c + 2];
+    ac[DM_NACC_HEAD] += m20;
+    ac[DM_ACC_NSAMPLES] += 1.0;
+    ac[DM_ACC_BOND] += o[DM_CO_BOND];
+    ac[DM_ACC_BOND2] += o[DM_CO_BOND2];
+    ac[DM_ACC_L2] += o[DM_CO_L2];
+    ac[DM_ACC_MSDCM] += dx * dx + dy * dy + dz * dz;
+    ac[DM_ACC_DMID2] += o[DM_CO_DMID] * o[DM_CO_DMID] + o[DM_CO_DMID + 1] * o[DM_CO_DMID + 1] +
+                        o[DM_CO_DMID + 2] * o[DM_CO_DMID + 2];
+    ac[DM_ACC_XSPAN] += o[DM_CO_XSPAN];
+    // tumbling in the flow plane, with hysteresis (as the FP64 path)
+    const double rho = sqrt(Lx * Lx + Ly * Ly);
+    const double s0 = a.tstate[c];
+    const double s1 = Lx > 0.5 * rho ? 1.0 : (Lx < -0.5 * rho ? -1.0 : s0);
+    if (s0 != 0.0 && s1 != s0) {
+        const double k = (double)*a.step;
+        ac[DM_ACC_TUMBLES] += 1.0;
+        if (a.tlast[c] > 0.0) {
+            const double tau = k - (a.tlast[c] - 1.0);
+            ac[DM_ACC_TAU] += tau;
+            ac[DM_ACC_TAU2] += tau * tau;
+            ac[DM_ACC_NTAU] += 1.0;
+            ac[DM_NACC_HEAD + M + min(DM_NTUMBLE_BINS - 1, max(0, ilogb(tau)))] += 1.0;
+        }
+        a.tlast[c] = k + 1.0;
+    }
+    a.tstate[c] = s1;
+}
+
 // FP64 amplitudes [chain][component][p] -> fused state (even modes scaled
 // by sigma_p, sig[p/2 - 1]) and back.
 __global__ void pack_kernel(const double *__restrict__ R64, const double *__restrict__ sig,
@@ -668,7 +836,29 @@ hipError_t fused_alloc(FusedBucket &f, int M, int n, bool bf16)
         hipSuccess)
         return e;
     if ((e = hipMemset(f.d_X, 0, xb)) != hipSuccess) return e;
-    return hipMemset(f.d_R, 0, sizeof(float) * state_floats(RT, f.ntiles));
+    if ((e = hipMemset(f.d_R, 0, sizeof(float) * state_floats(RT, f.ntiles))) != hipSuccess)
+        return e;
+    // observation tables: rows n (bead), K slot j; fragment (I, t, kind)
+    const double c1 = std::sqrt(2.0 / M);
+    std::vector<float> P((size_t)2 * RT * RT * 256, 0.0f);
+    for (int I = 0; I < RT; ++I)
+        for (int t = 0; t < RT; ++t)
+            for (int kind = 0; kind < 2; ++kind)
+                for (int l = 0; l < 64; ++l)
+                    for (int r = 0; r < 4; ++r) {
+                        const int nb = 16 * I + l % 16, j = 16 * t + 4 * (l / 16) + r;
+                        const int p = kind == 0 ? 2 * j + 1 : 2 * j + 2;
+                        double v = 0.0;
+                        if (nb < H && p < M) {
+                            // cos(p (n + 1/2) pi / M) = cos(pi p (2n + 1) / 2M)
+                            v = c1 * std::cos(kPi * (double)((long)p * (2 * nb + 1) % (4L * M)) /
+                                              (2.0 * M));
+                            if (kind == 1) v /= sig[j];
+                        }
+                        P[((((size_t)I * RT + t) * 2 + kind) * 64 + l) * 4 + r] = (float)v;
+                    }
+    if ((e = hipMalloc((void **)&f.d_P, sizeof(float) * P.size())) != hipSuccess) return e;
+    return hipMemcpy(f.d_P, P.data(), sizeof(float) * P.size(), hipMemcpyHostToDevice);
 }
 
 // Write both products' fragments (layout at fused_kernel) for step
@@ -740,6 +930,7 @@ void fused_free(FusedBucket &f)
     if (f.d_R0) (void)hipFree(f.d_R0);
     if (f.d_coef) (void)hipFree(f.d_coef);
     if (f.d_sig) (void)hipFree(f.d_sig);
+    if (f.d_P) (void)hipFree(f.d_P);
     f = FusedBucket();
 }
 
@@ -1106,6 +1297,47 @@ hipError_t fused_set_step(int64_t *d_step, int64_t value, hipStream_t st)
 hipError_t fused_advance_step(int64_t *d_step, int64_t n, hipStream_t st)
 {
     hipLaunchKernelGGL(set_step_kernel, dim3(1), dim3(64), 0, st, d_step, (int64_t)0, n);
+    return hipGetLastError();
+}
+
+template <int RT>
+static void launch_obs(const ObsArgs &a, int ntiles, hipStream_t st)
+{
+    hipLaunchKernelGGL(fused_obs_kernel<RT>, dim3(ntiles), dim3(64),
+                       sizeof(float) * 16 * (size_t)a.M, st, a);
+}
+
+hipError_t fused_observe(const FusedBucket &f, int M, double *obs, double *m2, double *acc,
+                         const double *cm0, double *tstate, double *tlast,
+                         const int64_t *d_step, int accumulate, hipStream_t st)
+{
+    if (f.n <= 0) return hipSuccess;
+    ObsArgs a;
+    a.R = f.d_R;
+    a.R0 = f.d_R0;
+    a.P = f.d_P;
+    a.sig = f.d_sig;
+    a.obs = obs;
+    a.m2 = m2;
+    a.acc = acc;
+    a.cm0 = cm0;
+    a.tstate = tstate;
+    a.tlast = tlast;
+    a.step = d_step;
+    a.M = M;
+    a.n = f.n;
+    a.accumulate = accumulate;
+    switch (f.RT) {
+    case 2: launch_obs<2>(a, f.ntiles, st); break;
+    case 4: launch_obs<4>(a, f.ntiles, st); break;
+    case 6: launch_obs<6>(a, f.ntiles, st); break;
+    case 8: launch_obs<8>(a, f.ntiles, st); break;
+    case 10: launch_obs<10>(a, f.ntiles, st); break;
+    case 12: launch_obs<12>(a, f.ntiles, st); break;
+    case 14: launch_obs<14>(a, f.ntiles, st); break;
+    case 16: launch_obs<16>(a, f.ntiles, st); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

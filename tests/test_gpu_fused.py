@@ -157,3 +157,27 @@ def test_fused_uneven_ensemble(prec):
                               seed=2, chain_ids=[c])
         err = rel_pos_err(got[c][None], oracle.positions_from_modes(R))
         assert err < 3 * ONE_STEP_TOL[prec], (c, M, err)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("M", [2, 64, 96, 256, 512])
+def test_fused_observables_match_fp64_of_the_same_state(prec, M):
+    """The fused observation kernel (FP32 MFMA positions from the FP32 state)
+    against the oracle's observables of the FP64 positions and amplitudes of
+    the same state: FP32 rounding of positions of size ~M b."""
+    B = 12
+    pos = inputs.straight_chains(B, M, B_FAC, seed=M + 7, random_orientation=True)
+    with Context(pos, seed=4, precision=prec) as ctx:
+        ctx.set_params([M], [DTAU.get(M, 10.0)], T_star=TS, nu=NU)
+        ctx.step_modes(30)
+        got = ctx.chain_observables()
+        m2 = ctx.observables(_lib.DM_OBS_MODES).reshape(B, M)
+        p64, R64 = ctx.positions(), ctx.modes()
+    want = oracle.chain_observables(p64)
+    scale = (M - 1) * B_FAC
+    for k, name in enumerate(oracle.OBS_NAMES):
+        unit = {"L2": scale ** 2, "bond2_mean": B_FAC ** 2}.get(name, scale)
+        err = np.abs(got[:, k] - want[:, k]).max() / unit
+        assert err < 2e-6, (name, err)
+    want_m2 = (R64 ** 2).sum(axis=1)
+    assert np.allclose(m2, want_m2, rtol=2e-6, atol=1e-12 * want_m2.max())
