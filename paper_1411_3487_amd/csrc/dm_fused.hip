@@ -352,35 +352,51 @@ __device__ __forceinline__ void fused_tiles(const BucketArgs &a, const LaunchArg
                         split_bf16(Ro[2 * q], Ro[2 * q + 1], boh, bol);
                         split_bf16(Re[2 * q], Re[2 * q + 1], beh, bel);
                     }
+                    // all fragments of the half slab first, then each product over
+                    // the HALF row tiles: HALF independent accumulator pairs between
+                    // two MFMAs into the same accumulator
+                    bf16x8 xoh[HALF], xol[HALF], xeh[HALF], xel[HALF];
 #pragma unroll
                     for (int ii = 0; ii < HALF; ++ii) {
-                        const int I = h * HALF + ii;
                         const f32x4 *fr = xs + (ii * 4) * 64 + lane;
-                        const bf16x8 xoh = __builtin_bit_cast(bf16x8, fr[0]);
-                        const bf16x8 xol = __builtin_bit_cast(bf16x8, fr[64]);
-                        const bf16x8 xeh = __builtin_bit_cast(bf16x8, fr[128]);
-                        const bf16x8 xel = __builtin_bit_cast(bf16x8, fr[192]);
-                        aS[I] = mfma_bf16(xoh, boh, aS[I]);
-                        aA[I] = mfma_bf16(xeh, beh, aA[I]);
-                        aS[I] = mfma_bf16(xoh, bol, aS[I]);
-                        aA[I] = mfma_bf16(xeh, bel, aA[I]);
-                        aS[I] = mfma_bf16(xol, boh, aS[I]);
-                        aA[I] = mfma_bf16(xel, beh, aA[I]);
+                        xoh[ii] = __builtin_bit_cast(bf16x8, fr[0]);
+                        xol[ii] = __builtin_bit_cast(bf16x8, fr[64]);
+                        xeh[ii] = __builtin_bit_cast(bf16x8, fr[128]);
+                        xel[ii] = __builtin_bit_cast(bf16x8, fr[192]);
+                    }
+#pragma unroll
+                    for (int ii = 0; ii < HALF; ++ii) {
+                        aS[h * HALF + ii] = mfma_bf16(xoh[ii], boh, aS[h * HALF + ii]);
+                        aA[h * HALF + ii] = mfma_bf16(xeh[ii], beh, aA[h * HALF + ii]);
+                    }
+#pragma unroll
+                    for (int ii = 0; ii < HALF; ++ii) {
+                        aS[h * HALF + ii] = mfma_bf16(xoh[ii], bol, aS[h * HALF + ii]);
+                        aA[h * HALF + ii] = mfma_bf16(xeh[ii], bel, aA[h * HALF + ii]);
+                    }
+#pragma unroll
+                    for (int ii = 0; ii < HALF; ++ii) {
+                        aS[h * HALF + ii] = mfma_bf16(xol[ii], boh, aS[h * HALF + ii]);
+                        aA[h * HALF + ii] = mfma_bf16(xel[ii], beh, aA[h * HALF + ii]);
                     }
                 } else {
 #pragma unroll
-                    for (int ii = 0; ii < HALF; ++ii) {
-                        const int I = h * HALF + ii;
-                        const f32x4 *fr = xs + (ii * 4) * 64 + lane;
+                    for (int hh = 0; hh < 2; ++hh) {
+                        // fragments first, then K slice r over the HALF row tiles
+                        f32x4 xo[HALF], xe[HALF];
 #pragma unroll
-                        for (int hh = 0; hh < 2; ++hh) {
-                            const f32x4 xo = fr[hh * 64], xe = fr[(2 + hh) * 64];
-#pragma unroll
-                            for (int r = 0; r < 4; ++r) {
-                                aS[I] = mfma_f32(xo[r], Ro[2 * q + hh][r], aS[I]);
-                                aA[I] = mfma_f32(xe[r], Re[2 * q + hh][r], aA[I]);
-                            }
+                        for (int ii = 0; ii < HALF; ++ii) {
+                            xo[ii] = xs[(ii * 4 + hh) * 64 + lane];
+                            xe[ii] = xs[(ii * 4 + 2 + hh) * 64 + lane];
                         }
+#pragma unroll
+                        for (int r = 0; r < 4; ++r)
+#pragma unroll
+                            for (int ii = 0; ii < HALF; ++ii) {
+                                const int I = h * HALF + ii;
+                                aS[I] = mfma_f32(xo[ii][r], Ro[2 * q + hh][r], aS[I]);
+                                aA[I] = mfma_f32(xe[ii][r], Re[2 * q + hh][r], aA[I]);
+                            }
                     }
                 }
                 finish(t, s);
@@ -462,19 +478,26 @@ __device__ __forceinline__ void fused_tiles(const BucketArgs &a, const LaunchArg
                 }
                 f32x4 ce = f32x4{0.f, 0.f, 0.f, 0.f};
                 if constexpr (BF16) {
+                    // alternate slabs go to a second accumulator pair, so two
+                    // MFMA chains are in flight
+                    f32x4 ao2 = f32x4{0.f, 0.f, 0.f, 0.f}, ce2 = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                     for (int q = 0; q < KS; ++q) {
                         const bf16x8 xoh = __builtin_bit_cast(bf16x8, xo2[(2 * q) * 64]);
                         const bf16x8 xol = __builtin_bit_cast(bf16x8, xo2[(2 * q + 1) * 64]);
                         const bf16x8 xeh = __builtin_bit_cast(bf16x8, xe2[(ES * q) * 64]);
                         const bf16x8 xel = __builtin_bit_cast(bf16x8, xe2[(ES * q + 1) * 64]);
-                        ao = mfma_bf16(xoh, gph[q], ao);
-                        ce = mfma_bf16(xeh, gmh[q], ce);
-                        ao = mfma_bf16(xoh, gpl[q], ao);
-                        ce = mfma_bf16(xeh, gml[q], ce);
-                        ao = mfma_bf16(xol, gph[q], ao);
-                        ce = mfma_bf16(xel, gmh[q], ce);
+                        f32x4 &A = (q & 1) ? ao2 : ao;
+                        f32x4 &C = (q & 1) ? ce2 : ce;
+                        A = mfma_bf16(xoh, gph[q], A);
+                        C = mfma_bf16(xeh, gmh[q], C);
+                        A = mfma_bf16(xoh, gpl[q], A);
+                        C = mfma_bf16(xeh, gml[q], C);
+                        A = mfma_bf16(xol, gph[q], A);
+                        C = mfma_bf16(xel, gmh[q], C);
                     }
+                    ao += ao2;
+                    ce += ce2;
                 } else {
 #pragma unroll
                     for (int q = 0; q < KS; ++q) {
