@@ -31,6 +31,9 @@ def parse():
                          "64..512 bp in one launch; shear: 2048 x 256 bp under simple shear "
                          "at Wi = 1, 10, 100 (tumbling and extension, FP32 vs FP64)")
     ap.add_argument("--shear-steps", type=int, default=1000000)
+    ap.add_argument("--profile-launches", type=int, default=0, metavar="N",
+                    help="only run N fused launches of 200 steps of the default workload "
+                         "(for hardware-counter passes) and exit")
     ap.add_argument("--steps", type=int, default=20000)
     ap.add_argument("--warmup", type=int, default=1000)
     ap.add_argument("--precision", default="bf16x3", choices=["bf16x3", "fp32"])
@@ -217,8 +220,27 @@ def shear_workload(args):
                       "precision": prec, "results": res}))
 
 
+def profile_launches(args):
+    """N launches of 200 mode steps of the default workload, no sampling."""
+    import torch
+    from paper_1411_3487_amd import Context, inputs, NU_DSDNA, T_STAR_DSDNA
+    torch.cuda.set_device(0)
+    b = 1.0 / (1.0 - 2.0 * NU_DSDNA)
+    pos = inputs.straight_chains(args.chains, args.beads, b, seed=1, random_orientation=True)
+    ctx = Context(pos, seed=1, precision=args.precision, stream=torch.cuda.current_stream())
+    ctx.set_params([args.beads], [args.dtau], T_star=T_STAR_DSDNA, nu=NU_DSDNA)
+    for _ in range(args.profile_launches):
+        ctx.step_modes(200)
+    torch.cuda.synchronize()
+    print(json.dumps({"profile_launches": args.profile_launches, "steps_per_launch": 200,
+                      "tiling": {k: float(v) for k, v in ctx.tiling()[0].items()}}))
+    ctx.close()
+
+
 def main():
     args = parse()
+    if args.profile_launches:
+        return profile_launches(args)
     if args.workload != "modes" and args.gpus == 1:
         return uneven_workload(args) if args.workload == "uneven" else shear_workload(args)
     if args.copy_calibration:
