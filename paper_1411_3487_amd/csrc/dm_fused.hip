@@ -576,10 +576,10 @@ __device__ __forceinline__ size_t state_slot(int j, int alpha, int p, int RT)
     return (((size_t)T * 2 + set) * RT + t) * 256 + (size_t)lane * 4 + (rho % 4);
 }
 
-// Observables of the fused state, one wavefront per tile.  Positions
+// Observables of the fused state, one workgroup of 4 wavefronts per tile.  Positions
 // relative to the centre of mass, r_n - r_cm = sum_{p >= 1} phi_{n,p} R_p
 // (Eq. c1; the internal modes sum to zero over the beads), in the mirror
-// halves of Sec. 5a: for beads n < H
+// halves of Sec. 5a (the 4 wavefronts share the row tiles): for beads n < H
 //   O_n = sum_{p odd} phi_{n,p} R_p,  E_n = sum_{p even} phi_{n,p} R_p,
 //   r_n = E_n + O_n,  r_{M-1-n} = E_n - O_n,
 // as FP32 MFMA products with the tables P (odd: phi_{n,2j+1}; even:
@@ -601,11 +601,12 @@ struct ObsArgs {
 };
 
 template <int RT>
-__global__ __launch_bounds__(64) void fused_obs_kernel(ObsArgs a)
+__global__ __launch_bounds__(256) void fused_obs_kernel(ObsArgs a)
 {
     extern __shared__ float pos[];  // [16][M]
     const int M = a.M, H = M / 2, tile = blockIdx.x;
-    const int lane = threadIdx.x, col = lane & 15, g = lane >> 4;
+    const int lane = threadIdx.x & 63, col = lane & 15, g = lane >> 4;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int cl = col / 3, alpha = col - 3 * cl;
     const int nvalid = min(kChainsPerTile, a.n - kChainsPerTile * tile);
     f32x4 Ro[RT], Re[RT];
@@ -616,7 +617,7 @@ __global__ __launch_bounds__(64) void fused_obs_kernel(ObsArgs a)
         Re[t] = Rt[(1 * RT + t) * 64 + lane];
     }
     const f32x4 *P = reinterpret_cast<const f32x4 *>(a.P);
-    for (int I = 0; I < RT; ++I) {
+    for (int I = wave; I < RT; I += 4) {
         f32x4 o = f32x4{0.f, 0.f, 0.f, 0.f}, e = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int t = 0; t < RT; ++t) {
@@ -637,6 +638,8 @@ __global__ __launch_bounds__(64) void fused_obs_kernel(ObsArgs a)
             }
         }
     }
+    __syncthreads();
+    if (wave != 0) return;  // the rest is one wavefront's
     // |R_p|^2 of p >= 1, summed over the chain's three component lanes
     const int W = acc_width(M);
     for (int t = 0; t < RT; ++t) {
@@ -660,7 +663,6 @@ __global__ __launch_bounds__(64) void fused_obs_kernel(ObsArgs a)
             }
         }
     }
-    __syncthreads();
     // 8 lanes per chain: bond lengths and the x extent
     const int c8 = lane >> 3, part = lane & 7;
     const bool cv = c8 < nvalid;
@@ -1326,7 +1328,7 @@ hipError_t fused_advance_step(int64_t *d_step, int64_t n, hipStream_t st)
 template <int RT>
 static void launch_obs(const ObsArgs &a, int ntiles, hipStream_t st)
 {
-    hipLaunchKernelGGL(fused_obs_kernel<RT>, dim3(ntiles), dim3(64),
+    hipLaunchKernelGGL(fused_obs_kernel<RT>, dim3(ntiles), dim3(256),
                        sizeof(float) * 16 * (size_t)a.M, st, a);
 }
 
