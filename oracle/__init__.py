@@ -67,6 +67,7 @@ def _load():
         "orc_bead_force": (None, [_i, _d, _p, _p]),
         "orc_step_euler": (None, [_i, _i, _p, _p, _d, _d, _d, _d, _u64, _i64, _i64]),
         "orc_energy": (_d, [_i, _d, _p]),
+        "orc_mc_sweeps": (None, [_i, _i, _p, _p, _d, _d, _d, _u64, _i64, _i64, _p]),
         "orc_chain_observables": (None, [_i, _p, _p]),
     }
     for name, (res, args) in sig.items():
@@ -194,6 +195,20 @@ def step_euler(pos, nu, T_star, dtau, n_steps, seed=0, step0=0, chain_ids=None,
     lib.orc_step_euler(M, B, _ptr(ids), _ptr(pos), nu, T_star, dtau, gamma_dot,
                        seed, step0, n_steps)
     return pos
+
+
+def mc_sweeps(R, nu, T_star, scale, n_sweeps, seed=0, step0=0, chain_ids=None):
+    """Metropolis sweeps of the mode amplitudes R (B, 3, M) (see
+    orc_mc_sweeps); returns (R after the sweeps, accepted proposals per chain)."""
+    lib = _load()
+    R = _f64(R).copy()
+    B, _, M = R.shape
+    ids = np.arange(B, dtype=np.uint32) if chain_ids is None else \
+        np.ascontiguousarray(chain_ids, dtype=np.uint32)
+    acc = np.zeros(B, dtype=np.int64)
+    lib.orc_mc_sweeps(M, B, _ptr(ids), _ptr(R), nu, T_star, scale, seed, step0, n_sweeps,
+                      _ptr(acc))
+    return R, acc
 
 
 def energy(pos, nu) -> float:

@@ -378,6 +378,76 @@ double orc_energy(int M, double nu, const double *pos)
 }
 
 /* ------------------------------------------------------------------------ */
+/* Metropolis Monte Carlo in the mode representation, the paper's           */
+/* equilibrium benchmark (Sec. 6: "large MC steps in the slow modes and     */
+/* small steps in the fast modes").  The paper gives no more detail; this   */
+/* is the reading used.  One sweep proposes, for p = 1..M-1 and component   */
+/* a = x, y, z in that order, R_p^a -> R_p^a + delta with delta uniform on  */
+/* (-s_p, s_p), s_p = scale * sqrt(T* / zeta^l_p) (the width of mode p      */
+/* under the harmonic Hamiltonian of Eqs. c6, c9), and accepts it with      */
+/* probability min(1, exp(-(H'_new - H'_old) / T*)), H' of Eq. (b3) on the  */
+/* positions.  Random numbers: the Philox block of counter (p, chain,       */
+/* step = sweep index, component a, tag 2); word 0 gives delta =            */
+/* s_p (2 U0 - 1), word 1 the uniform U1 of the test U1 < exp(-dH'/T*),    */
+/* U = (x + 1/2) 2^-32.  The centre of mass does not enter H' and is left   */
+/* unchanged.  accepted[c] receives the number of accepted proposals.      */
+/* ------------------------------------------------------------------------ */
+void orc_mc_sweeps(int M, int n_chains, const uint32_t *chain_id, double *R,
+                   double nu, double T_star, double scale, uint64_t seed,
+                   int64_t step0, int64_t n_sweeps, int64_t *accepted)
+{
+    double *phi = malloc(sizeof(double) * M * M);
+    double *zl = malloc(sizeof(double) * M), *z = malloc(sizeof(double) * M);
+    double *E = malloc(sizeof(double) * M), *C = malloc(sizeof(double) * M);
+    double *W = malloc(sizeof(double) * M);
+    orc_tables(M, nu, T_star, 1.0, phi, zl, z, E, C, W);
+    const double two_m32 = 1.0 / 4294967296.0;
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+
+#pragma omp parallel
+    {
+        double *r = malloc(sizeof(double) * 3 * M);
+        double *rt = malloc(sizeof(double) * 3 * M);
+#pragma omp for schedule(dynamic, 1)
+        for (int c = 0; c < n_chains; ++c) {
+            double *Rc = R + (size_t)c * 3 * M;
+            int64_t acc = 0;
+            positions_from_modes(M, phi, Rc, 0, r);
+            double e = orc_energy(M, nu, r);
+            for (int64_t k = step0; k < step0 + n_sweeps; ++k) {
+                const uint64_t ku = (uint64_t)k;
+                for (int p = 1; p < M; ++p) {
+                    const double sp = scale * sqrt(T_star / zl[p]);
+                    for (int a = 0; a < 3; ++a) {
+                        uint32_t ctr[4] = {(uint32_t)p, chain_id[c], (uint32_t)ku,
+                                           (uint32_t)((ku >> 32) << 8) |
+                                               ((uint32_t)a << 4) | 2u};
+                        uint32_t x[4];
+                        orc_philox4x32_10(ctr, key, x);
+                        const double u0 = ((double)x[0] + 0.5) * two_m32;
+                        const double u1 = ((double)x[1] + 0.5) * two_m32;
+                        const double delta = sp * (2.0 * u0 - 1.0);
+                        memcpy(rt, r, sizeof(double) * 3 * M);
+                        for (int n = 0; n < M; ++n)
+                            rt[a * M + n] += phi[n * M + p] * delta;
+                        const double et = orc_energy(M, nu, rt);
+                        if (u1 < exp(-(et - e) / T_star)) {
+                            memcpy(r, rt, sizeof(double) * 3 * M);
+                            Rc[a * M + p] += delta;
+                            e = et;
+                            ++acc;
+                        }
+                    }
+                }
+            }
+            accepted[c] = acc;
+        }
+        free(r); free(rt);
+    }
+    free(phi); free(zl); free(z); free(E); free(C); free(W);
+}
+
+/* ------------------------------------------------------------------------ */
 /* Observables of Sec. 5b: per chain, from positions (3*M).                 */
 /* out[0] mean bond length, out[1] |L|^2 with L = r_{M-1} - r_0,            */
 /* out[2..4] L, out[5..7] centre of mass, out[8..10] middle bond            */

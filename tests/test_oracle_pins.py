@@ -523,3 +523,73 @@ def test_tumble_histogram_octaves():
     for b in (0, 1, 1, 2, 2, 3, 9, oracle.TUMBLE_BINS - 1):
         want[b] += 1
     assert np.array_equal(h, want)
+
+
+# ------------------------------------------------- Metropolis MC (equilibrium)
+def _mc_samples(M, B, T, n_burn, n_samp, every=1, seed=9, scale=3.0):
+    """Chains from near-straight starts, n_burn sweeps, then n_samp samples
+    every `every` sweeps; yields the mode amplitudes of each sample."""
+    pos = np.stack([near_straight(M, s, amp=0.05) for s in range(B)])
+    R = np.einsum("np,ban->bap", dct_phi(M), pos)
+    R, _ = oracle.mc_sweeps(R, NU, T, scale, n_burn, seed=seed)
+    step = n_burn
+    for _ in range(n_samp):
+        R, _ = oracle.mc_sweeps(R, NU, T, scale, every, seed=seed, step0=step)
+        step += every
+        yield R
+
+
+def test_mc_two_bead_equilibrium_by_quadrature():
+    l1, l2 = _two_bead_moments()
+    ell = []
+    for R in _mc_samples(2, 2000, TSTAR, 100, 40):
+        x = oracle.positions_from_modes(R)
+        ell.append(np.sqrt((np.diff(x, axis=2) ** 2).sum(axis=1)).ravel())
+    ell = np.concatenate(ell)
+    se = ell.std() / np.sqrt(ell.size / 4)     # consecutive sweeps correlate
+    assert ell.mean() == pytest.approx(l1, abs=5 * se)
+    assert (ell ** 2).mean() == pytest.approx(l2, abs=5 * 2 * se)
+
+
+def test_mc_three_bead_equilibrium_by_quadrature():
+    ml, dot, e2e = _three_bead_moments()
+    got_l, got_dot, got_e2e = [], [], []
+    for R in _mc_samples(3, 2000, TSTAR, 200, 30, every=2):
+        x = oracle.positions_from_modes(R)
+        u = np.diff(x, axis=2)
+        got_l.append(np.sqrt((u ** 2).sum(axis=1)).mean(axis=1))
+        got_dot.append((u[:, :, 0] * u[:, :, 1]).sum(axis=1))
+        got_e2e.append(((x[:, :, -1] - x[:, :, 0]) ** 2).sum(axis=1))
+    for got, ref in [(got_l, ml), (got_dot, dot), (got_e2e, e2e)]:
+        g = np.concatenate(got)
+        se = g.std() / np.sqrt(g.size / 4)
+        assert abs(g.mean() - ref) < 5 * se, (g.mean(), ref, se)
+
+
+def test_mc_generalised_equipartition_per_mode():
+    """<R_p . dH'/dR_p> = 3 T* for every internal mode, dH'/dR_p =
+    zeta_p R_p - Delta H_p (Eq. e10): the sampler's stationary law is the
+    canonical one for a longer chain (M = 8, soft chain T* = 0.3)."""
+    M, B, T = 8, 400, 0.3
+    z = oracle.tables(M, NU, T, 1.0)["zeta"]
+    acc, n = np.zeros(M), 0
+    for R in _mc_samples(M, B, T, 300, 40, every=5):
+        for c in range(B):
+            dH = oracle.delta_h(R[c], NU)
+            acc += (R[c] * (z[None, :] * R[c] - dH)).sum(axis=0)
+        n += B
+    ratio = acc[1:] / n / (3 * T)
+    assert np.all(np.abs(ratio - 1) < 0.03), ratio
+
+
+def test_mc_sweep_is_reproducible_and_keeps_the_centre_of_mass():
+    pos = np.stack([near_straight(16, s) for s in range(3)])
+    R = np.einsum("np,ban->bap", dct_phi(16), pos)
+    a, acc_a = oracle.mc_sweeps(R, NU, TSTAR, 3.0, 20, seed=4)
+    b, _ = oracle.mc_sweeps(R, NU, TSTAR, 3.0, 10, seed=4)
+    b, _ = oracle.mc_sweeps(b, NU, TSTAR, 3.0, 10, seed=4, step0=10)
+    assert np.array_equal(a, b)
+    assert np.array_equal(a[:, :, 0], R[:, :, 0])
+    assert np.all((acc_a > 0.4 * 20 * 45) & (acc_a < 0.75 * 20 * 45))
+    still, acc0 = oracle.mc_sweeps(R, NU, TSTAR, 0.0, 5, seed=4)
+    assert np.array_equal(still, R) and np.all(acc0 == 5 * 45)
