@@ -36,7 +36,8 @@
  *    (seed lo, seed hi) and counter (index/4, chain, step lo,
  *    (step hi << 8) | (component << 4) | tag); the four outputs give two
  *    Box-Muller pairs, normal j of the block belongs to index 4*(index/4)+j.
- *    tag 0 = mode step (index = mode p), 1 = Euler step (index = bead n).
+ *    tag 0 = mode step (index = mode p), 1 = Euler step (index = bead n),
+ *    2 = Monte Carlo sweep (index = mode p, see dm_step_mc).
  *    Results are therefore independent of how chains are batched.
  */
 #ifndef DNAMODES_H
@@ -193,6 +194,25 @@ int dm_step_modes(dm_ctx *ctx, int64_t n_steps);
    The scheme is unstable for dtau above about 0.3 (Sec. 3a).
    Errors: DM_ESTATE, DM_EINVAL (dtau <= 0), DM_ENONFINITE (check_finite). */
 int dm_step_euler(dm_ctx *ctx, int64_t n_steps, double dtau);
+
+/* Metropolis Monte Carlo in the mode representation, the paper's benchmark
+   for equilibrium values (Sec. 6: large steps in the slow modes, small in
+   the fast ones).  One sweep proposes, for p = 1..M-1 and component
+   a = x, y, z in order, R_p^a += delta, delta uniform on (-s_p, s_p) with
+   s_p = step_scale * sqrt(T* / zeta^l_p) (the width of mode p under the
+   harmonic Hamiltonian, Eqs. c6, c9), accepted with probability
+   min(1, exp(-dH'/T*)) for the reduced Hamiltonian H' of Eq. (b3); the
+   centre of mass is unchanged.  Philox counter (p, chain, sweep, a, tag 2):
+   word 0 gives delta = s_p (2 U0 - 1), word 1 the uniform U1 of the test
+   U1 < exp(-dH'/T*), U = (x + 1/2) 2^-32.  FP64 on every precision (the
+   fused state is converted in and out).  Sweeps advance the step counter;
+   observables are accumulated every sample_every sweeps as after mode
+   steps.  step_scale = 3 accepts about 56 % of the proposals.  *accepted
+   (host, may be NULL) receives the accepted proposals of the call, summed
+   over chains.  Synchronises the stream.  Errors: DM_ESTATE, DM_EINVAL
+   (n_sweeps < 0, step_scale < 0, M > 1365), DM_ENONFINITE (check_finite). */
+int dm_step_mc(dm_ctx *ctx, int64_t n_sweeps, double step_scale,
+               int64_t *accepted);
 
 /* Observables of Sec. 5b.  which = OR of DM_OBS_* bits; the selected blocks
    are written to out_host in the order CHAIN, MODES, ACCUM (see the layout

@@ -60,7 +60,7 @@ class dm_params(ctypes.Structure):
                 ("tiles_per_wg", ctypes.c_int32), ("table_mode", ctypes.c_int32)]
 
 
-EXPORTS = ["dm_init_chains", "dm_set_params", "dm_step_modes", "dm_step_euler",
+EXPORTS = ["dm_init_chains", "dm_set_params", "dm_step_modes", "dm_step_euler", "dm_step_mc",
            "dm_observables", "dm_observables_size", "dm_get_positions", "dm_get_modes",
            "dm_save_state", "dm_load_state", "dm_get_step", "dm_get_tiling",
            "dm_tuning_report", "dm_sync", "dm_destroy", "dm_last_error"]
@@ -84,6 +84,7 @@ def load(path: str = LIB_PATH):
         "dm_set_params": ([vp, ctypes.POINTER(dm_params)], ctypes.c_int),
         "dm_step_modes": ([vp, i64], ctypes.c_int),
         "dm_step_euler": ([vp, i64, ctypes.c_double], ctypes.c_int),
+        "dm_step_mc": ([vp, i64, ctypes.c_double, ctypes.POINTER(i64)], ctypes.c_int),
         "dm_observables": ([vp, i32, vp, sz], ctypes.c_int),
         "dm_observables_size": ([vp, i32, ctypes.POINTER(sz)], ctypes.c_int),
         "dm_get_positions": ([vp, vp, i32], ctypes.c_int),
@@ -198,6 +199,12 @@ class Context:
 
     def step_euler(self, n_steps: int, dtau: float):
         self._check(self.lib.dm_step_euler(self.h, n_steps, dtau))
+
+    def step_mc(self, n_sweeps: int, step_scale: float = 3.0) -> int:
+        """Metropolis sweeps; returns the number of accepted proposals."""
+        acc = ctypes.c_int64()
+        self._check(self.lib.dm_step_mc(self.h, n_sweeps, step_scale, ctypes.byref(acc)))
+        return acc.value
 
     def observables_size(self, which: int) -> int:
         n = ctypes.c_size_t()

@@ -41,6 +41,12 @@ struct Bucket {
     double *d_acc = nullptr;         // n*acc_width(M)
     double *d_accsum = nullptr;      // acc_width(M)
     double *d_tumble = nullptr;      // 2n: tumbling state, step of the last tumble + 1
+    // Metropolis sampler (allocated on first use)
+    double *d_chiT = nullptr;        // chi_{n,p} at [p][n-1], M x (M-1)
+    double *d_mcstep = nullptr;      // proposal half-widths s_p
+    int64_t *d_mcacc = nullptr;      // accepted proposals per chain
+    std::vector<double> zeta_l;      // host zeta^l_p of the current parameters
+    std::vector<double> mcstep_h;    // host copy of s_p (kept alive for the upload)
     double *d_cm0 = nullptr;         // n*3
     dm::FusedBucket fused;           // reduced-precision state and tables
 };
@@ -115,7 +121,8 @@ void free_bucket(Bucket &b)
 {
     void *ptrs[] = {b.d_ids, b.d_off,  b.d_Ainv, b.d_Apos, b.d_Afwd, b.d_E,   b.d_C,
                     b.d_W,   b.d_R64, b.d_r,    b.d_F,    b.d_dH,   b.d_obs, b.d_m2,
-                    b.d_acc, b.d_accsum, b.d_cm0, b.d_tumble};
+                    b.d_acc, b.d_accsum, b.d_cm0, b.d_tumble, b.d_chiT, b.d_mcstep,
+                    b.d_mcacc};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     dm::fused_free(b.fused);
@@ -426,6 +433,7 @@ int dm_set_params(dm_ctx *ctx, const dm_params *p)
                                             ctx->stream));
         DM_HIP(ctx, hipStreamSynchronize(ctx->stream));  // host tables go out of scope
         b.dtau = dtau[i];
+        b.zeta_l = mc.zeta_l;
     }
     ctx->T_star = T_star;
     ctx->nu = nu;
@@ -522,6 +530,70 @@ int dm_step_euler(dm_ctx *ctx, int64_t n_steps, double dtau)
             DM_HIP(ctx, dm::fused_pack_modes(b.fused, b.d_R64, b.M, b.n, ctx->stream));
     }
     ctx->step += n_steps;
+    if (ctx->check_finite) return check_state(ctx);
+    return DM_OK;
+}
+
+int dm_step_mc(dm_ctx *ctx, int64_t n_sweeps, double step_scale, int64_t *accepted)
+{
+    if (!ctx) return DM_EINVAL;
+    if (!ctx->have_params) return fail(ctx, DM_ESTATE, "dm_set_params has not been called");
+    if (n_sweeps < 0 || n_sweeps > (1 << 30)) return fail(ctx, DM_EINVAL, "bad n_sweeps");
+    if (!(step_scale >= 0.0) || !std::isfinite(step_scale))
+        return fail(ctx, DM_EINVAL, "step_scale must be finite and >= 0");
+    for (Bucket &b : ctx->buckets)
+        if (48 * (size_t)b.M > 64 * 1024)
+            return fail(ctx, DM_EINVAL, "Monte Carlo needs M <= 1365 (LDS), got %d", b.M);
+    if (accepted) *accepted = 0;
+    if (n_sweeps == 0) return DM_OK;
+    const bool fused = fused_precision(ctx->precision);
+    for (Bucket &b : ctx->buckets) {
+        const int M = b.M, NB = M - 1;
+        if (!b.d_chiT) {
+            std::vector<double> phi, chiT((size_t)M * NB, 0.0);
+            dm::rouse_matrix(M, phi);
+            for (int p = 1; p < M; ++p)
+                for (int n = 1; n < M; ++n)
+                    chiT[(size_t)p * NB + n - 1] = phi[(size_t)n * M + p] - phi[(size_t)(n - 1) * M + p];
+            int rc;
+            if ((rc = dalloc(ctx, &b.d_chiT, chiT.size())) || (rc = dalloc(ctx, &b.d_mcstep, M)) ||
+                (rc = dalloc(ctx, &b.d_mcacc, b.n)))
+                return rc;
+            DM_HIP(ctx, hipMemcpy(b.d_chiT, chiT.data(), sizeof(double) * chiT.size(),
+                                  hipMemcpyHostToDevice));
+        }
+        b.mcstep_h.assign(M, 0.0);
+        for (int p = 1; p < M; ++p)
+            b.mcstep_h[p] = step_scale * std::sqrt(ctx->T_star / b.zeta_l[p]);
+        DM_HIP(ctx, hipMemcpyAsync(b.d_mcstep, b.mcstep_h.data(), sizeof(double) * M,
+                                   hipMemcpyHostToDevice, ctx->stream));
+        if (fused) DM_HIP(ctx, dm::fused_unpack_modes(b.fused, b.d_R64, b.M, b.n, ctx->stream));
+    }
+    int64_t done = 0, total = 0;
+    std::vector<int64_t> h;
+    while (done < n_sweeps) {
+        int64_t chunk = n_sweeps - done;
+        if (ctx->sample_every > 0)
+            chunk = std::min<int64_t>(chunk, ctx->sample_every - ctx->step % ctx->sample_every);
+        for (Bucket &b : ctx->buckets) {
+            DM_HIP(ctx, dm::launch_mc(b.d_R64, b.d_chiT, b.d_mcstep, b.d_ids, b.M, b.n, ctx->nu,
+                                      ctx->T_star, ctx->seed, ctx->step, (int)chunk, b.d_mcacc,
+                                      ctx->stream));
+            if (fused) DM_HIP(ctx, dm::fused_pack_modes(b.fused, b.d_R64, b.M, b.n, ctx->stream));
+            h.resize(b.n);
+            DM_HIP(ctx, hipMemcpyAsync(h.data(), b.d_mcacc, sizeof(int64_t) * b.n,
+                                       hipMemcpyDeviceToHost, ctx->stream));
+            DM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+            for (int64_t v : h) total += v;
+        }
+        ctx->step += chunk;
+        done += chunk;
+        if (ctx->sample_every > 0 && ctx->step % ctx->sample_every == 0) {
+            int rc = observe(ctx, 1, ctx->stream);
+            if (rc) return rc;
+        }
+    }
+    if (accepted) *accepted = total;
     if (ctx->check_finite) return check_state(ctx);
     return DM_OK;
 }

@@ -38,6 +38,13 @@ hipError_t launch_euler_f64(double *pos, const int32_t *ids, int M, int nch,
                             uint64_t seed, int64_t step0, int n_steps,
                             hipStream_t st);
 
+// n_sweeps Metropolis sweeps of the FP64 amplitudes R (nch chains of 3*M),
+// with chiT[p*(M-1) + n-1] = chi_{n,p} and step half-widths sstep[p]; the
+// accepted proposals of chain c go to accepted[c].
+hipError_t launch_mc(double *R, const double *chiT, const double *sstep, const int32_t *ids,
+                     int M, int nch, double nu, double T_star, uint64_t seed, int64_t step0,
+                     int n_sweeps, int64_t *accepted, hipStream_t st);
+
 // Per-chain observables from positions and modes; writes obs[c*16 + .] and
 // m2[c*M + p] = |R_p|^2, and adds into the per-chain accumulators
 // acc[c*acc_width(M) + .] when accumulate != 0, advancing the tumbling state

@@ -352,6 +352,80 @@ __global__ __launch_bounds__(64) void chain_obs_kernel(const double *__restrict_
     }
 }
 
+// Metropolis Monte Carlo in the mode representation, one wavefront per
+// chain (the paper's equilibrium benchmark, Sec. 6).  A sweep proposes, for
+// p = 1..M-1 and component a = x, y, z in order, R_p^a += delta with delta
+// uniform on (-s_p, s_p), and accepts with probability
+// min(1, exp(-dH'/T*)) for the reduced Hamiltonian of Eq. (b3).  The bond
+// vectors u_n (n = 1..M-1) live in LDS; a move shifts every bond by
+// chi_{n,p} delta along a, so dH' is a sum over bonds of the change of
+// (|u_n| - 1)^2 / 2 and of -nu u_n . u_{n+1}, reduced over the wavefront
+// (every lane ends with the same sum, hence the same decision).  Random
+// numbers: Philox block (p, chain, sweep, a, tag 2), word 0 for delta, word 1
+// for the acceptance test.
+__global__ __launch_bounds__(64) void mc_kernel(double *__restrict__ R,
+                                                const double *__restrict__ chiT,
+                                                const double *__restrict__ sstep,
+                                                const int32_t *__restrict__ ids, int M,
+                                                double nu, double T_star, uint64_t seed,
+                                                int64_t step0, int n_sweeps,
+                                                int64_t *__restrict__ accepted)
+{
+    extern __shared__ double mcl[];  // u[3][M-1], then the amplitudes R[3][M]
+    const int c = blockIdx.x, lane = threadIdx.x, NB = M - 1;
+    double *u = mcl, *Rl = mcl + 3 * NB;
+    double *Rc = R + (size_t)c * 3 * M;
+    const uint32_t chain = (uint32_t)ids[c];
+    for (int i = lane; i < 3 * M; i += 64) Rl[i] = Rc[i];
+    __syncthreads();
+    // u_n = sum_{p >= 1} chi_{n,p} R_p
+    for (int n = lane; n < NB; n += 64)
+        for (int a = 0; a < 3; ++a) {
+            double s = 0.0;
+            for (int p = 1; p < M; ++p) s += chiT[(size_t)p * NB + n] * Rl[a * M + p];
+            u[a * NB + n] = s;
+        }
+    __syncthreads();
+    int64_t acc = 0;
+    const double two_m32 = 2.3283064365386962890625e-10;
+    for (int s = 0; s < n_sweeps; ++s) {
+        const int64_t k = step0 + s;
+        for (int p = 1; p < M; ++p) {
+            const double sp = sstep[p];
+            const double *chi = chiT + (size_t)p * NB;
+            for (int a = 0; a < 3; ++a) {
+                const Block4 x = noise_bits(seed, (uint32_t)p, chain, k, (uint32_t)a, kTagMC);
+                const double u0 = ((double)x.v[0] + 0.5) * two_m32;
+                const double u1 = ((double)x.v[1] + 0.5) * two_m32;
+                const double delta = sp * (2.0 * u0 - 1.0);
+                double d = 0.0;
+                for (int n = lane; n < NB; n += 64) {
+                    const double ch = chi[n], ua = u[a * NB + n];
+                    const double ux = u[n], uy = u[NB + n], uz = u[2 * NB + n];
+                    const double l2 = ux * ux + uy * uy + uz * uz;
+                    const double l2n = l2 + ch * delta * (2.0 * ua + ch * delta);
+                    const double lo = sqrt(l2) - 1.0, ln = sqrt(l2n) - 1.0;
+                    d += 0.5 * (ln * ln - lo * lo);
+                    if (n + 1 < NB) {
+                        const double ch1 = chi[n + 1], ua1 = u[a * NB + n + 1];
+                        d -= nu * (delta * (ch * ua1 + ch1 * ua) + delta * delta * ch * ch1);
+                    }
+                }
+                d = wave_sum(d);
+                if (u1 < exp(-d / T_star)) {
+                    __syncthreads();  // every lane has read the old bonds
+                    for (int n = lane; n < NB; n += 64) u[a * NB + n] += chi[n] * delta;
+                    if (lane == 0) Rl[a * M + p] += delta;
+                    ++acc;
+                    __syncthreads();
+                }
+            }
+        }
+    }
+    for (int i = lane; i < 3 * M; i += 64) Rc[i] = Rl[i];
+    if (lane == 0) accepted[c] = acc;
+}
+
 __global__ void reduce_chains_kernel(const double *__restrict__ acc, double *__restrict__ out,
                                      int width, int nch)
 {
@@ -428,6 +502,18 @@ hipError_t launch_euler_f64(double *pos, const int32_t *ids, int M, int nch, dou
     if (lds > 64 * 1024) return hipErrorInvalidValue;  // positions must fit the LDS
     hipLaunchKernelGGL(euler_f64_kernel, dim3(nch), dim3(threads), lds, st, pos, ids, M, nu,
                        dtau, sqrt(2.0 * T_star * dtau), gdt, seed, step0, n_steps);
+    return hipGetLastError();
+}
+
+hipError_t launch_mc(double *R, const double *chiT, const double *sstep, const int32_t *ids,
+                     int M, int nch, double nu, double T_star, uint64_t seed, int64_t step0,
+                     int n_sweeps, int64_t *accepted, hipStream_t st)
+{
+    if (nch == 0 || n_sweeps == 0) return hipSuccess;
+    const size_t lds = sizeof(double) * (3 * (size_t)(M - 1) + 3 * (size_t)M);
+    if (M < 2 || lds > 64 * 1024) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(mc_kernel, dim3(nch), dim3(64), lds, st, R, chiT, sstep, ids, M, nu,
+                       T_star, seed, step0, n_sweeps, accepted);
     return hipGetLastError();
 }
 
