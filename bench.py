@@ -26,10 +26,13 @@ PEAKS = {"bf16x3": 2.5e15, "fp32": 157.3e12, "fp64": 78.6e12}  # dense MFMA, MI3
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", default="modes", choices=["modes", "uneven", "shear"],
+    ap.add_argument("--workload", default="modes",
+                    choices=["modes", "uneven", "shear", "mc", "dtmax"],
                     help="modes: 4096 x 256 bp (the headline line); uneven: 8192 chains of "
                          "64..512 bp in one launch; shear: 2048 x 256 bp under simple shear "
-                         "at Wi = 1, 10, 100 (tumbling and extension, FP32 vs FP64)")
+                         "at Wi = 1, 10, 100 (tumbling and extension, FP32 vs FP64); mc: "
+                         "Metropolis sweeps of 4096 x 256 bp; dtmax: equilibrium values of the "
+                         "mode dynamics against Monte Carlo over a range of time steps")
     ap.add_argument("--shear-steps", type=int, default=1000000)
     ap.add_argument("--profile-launches", type=int, default=0, metavar="N",
                     help="only run N fused launches of 200 steps of the default workload "
@@ -237,8 +240,95 @@ def profile_launches(args):
     ctx.close()
 
 
+def mc_workload(args):
+    """Metropolis sweeps (dm_step_mc, FP64) of 4096 chains x 256 bp."""
+    import torch
+    from paper_1411_3487_amd import Context, inputs, NU_DSDNA, T_STAR_DSDNA
+    torch.cuda.set_device(0)
+    b = 1.0 / (1.0 - 2.0 * NU_DSDNA)
+    B, M = args.chains, args.beads
+    pos = inputs.straight_chains(B, M, b, seed=1, random_orientation=True)
+    ctx = Context(pos, seed=1, precision="fp64", stream=torch.cuda.current_stream())
+    ctx.set_params([M], [args.dtau], T_star=T_STAR_DSDNA, nu=NU_DSDNA)
+    ctx.step_mc(2)
+    sweeps = 20
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    acc = ctx.step_mc(sweeps)
+    wall = time.perf_counter() - t0
+    ctx.close()
+    props = B * sweeps * 3 * (M - 1)
+    print(json.dumps({"metric": "Metropolis proposals/s (mode representation, FP64)",
+                      "value": props / wall, "unit": "proposals/s",
+                      "chain_sweeps_per_s": B * sweeps / wall, "acceptance": acc / props,
+                      "config": {"workload": f"{B} chains x {M} bp, {sweeps} sweeps, "
+                                             "step_scale 3"}}))
+
+
+def dtmax_workload(args):
+    """Equilibrium values Q(0) of the mode dynamics (Sec. 6: <L^2>, middle
+    bead about the centre of mass, bond moments) for several time steps,
+    each divided by its Metropolis value; the paper accepts a time step
+    while all ratios stay within 5 %.  Chains are equilibrated by Monte
+    Carlo first, and every dynamics run starts from that state."""
+    import numpy as np
+    import torch
+    from paper_1411_3487_amd import Context, inputs, NU_DSDNA, T_STAR_DSDNA
+    torch.cuda.set_device(0)
+    b = 1.0 / (1.0 - 2.0 * NU_DSDNA)
+    # time steps bracketing the paper's Table 1 (50, 100, 100 at N = 63, 127,
+    # 255); Monte Carlo burn-in and sampling sweeps
+    plan = {64: ([1, 10, 20, 50, 100, 200, 500], 3000, 6000),
+            128: ([10, 50, 100, 200, 500, 1000], 8000, 12000),
+            256: ([100, 200, 500, 1000, 2000], 20000, 20000)}
+    B = 1024
+    keys = ("L2", "dmid2", "bond", "bond2")
+    out = []
+    for M, (dts, burn, samp) in plan.items():
+        pos = inputs.straight_chains(B, M, b, seed=M, random_orientation=True)
+        t0 = time.perf_counter()
+        mc = Context(pos, seed=M, precision="fp64")
+        mc.set_params([M], [1.0], T_star=T_STAR_DSDNA, nu=NU_DSDNA, sample_every=20)
+        mc.step_mc(burn)
+        state = mc.positions()
+        mc.accumulators(reset=True)
+        mc.step_mc(samp)
+        a = mc.accumulators()[0]
+        ref = {k: a[k] / a["n_samples"] for k in keys}
+        mc.close()
+        print(f"# M={M}: Monte Carlo {burn}+{samp} sweeps, {time.perf_counter() - t0:.0f} s",
+              file=sys.stderr, flush=True)
+        z1 = 16 * NU_DSDNA * np.sin(np.pi / (2 * M)) ** 4
+        rows = []
+        for dt in dts:
+            # relax 2/zeta_1 from the Monte Carlo state, then average 2/zeta_1
+            n = max(2000, int(round(2.0 / z1 / dt)))
+            ctx = Context(state, seed=M + 1, precision=args.precision)
+            ctx.set_params([M], [float(dt)], T_star=T_STAR_DSDNA, nu=NU_DSDNA,
+                           sample_every=max(1, n // 400), use_graphs=True)
+            ctx.step_modes(n)
+            ctx.accumulators(reset=True)
+            ctx.step_modes(n)
+            d = ctx.accumulators()[0]
+            ctx.close()
+            ratio = {k: d[k] / d["n_samples"] / ref[k] for k in keys}
+            rows.append({"dtau": dt, "steps": 2 * n, "ratios": ratio,
+                         "within_5pct": all(abs(r - 1) < 0.05 for r in ratio.values())})
+            print(f"# M={M} dtau={dt}: {ratio}", file=sys.stderr, flush=True)
+        ok = [r["dtau"] for r in rows if r["within_5pct"]]
+        out.append({"M": M, "N": M - 1, "mc_reference": ref, "runs": rows,
+                    "dtau_max_from_Q0": max(ok) if ok else None})
+    print(json.dumps({"workload": f"dtau_max from equilibrium values, {B} chains per length, "
+                                  f"{args.precision} mode dynamics vs FP64 Monte Carlo",
+                      "results": out}))
+
+
 def main():
     args = parse()
+    if args.workload == "mc" and args.gpus == 1:
+        return mc_workload(args)
+    if args.workload == "dtmax" and args.gpus == 1:
+        return dtmax_workload(args)
     if args.profile_launches:
         return profile_launches(args)
     if args.workload != "modes" and args.gpus == 1:

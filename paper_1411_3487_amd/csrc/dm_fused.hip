@@ -59,6 +59,8 @@ namespace {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 
 constexpr int kChainsPerTile = 5;
 
@@ -110,17 +112,27 @@ __device__ __forceinline__ float comp_sum(float v, int alpha)
     return alpha == 0 ? s : (alpha == 1 ? s1 : s2);
 }
 
-// x = hi + lo with hi = bf16(x) and lo = bf16(x - hi), for the 8 K-slots of
-// a slab made of two 16-row result tiles.
+// x = hi + lo with hi = bf16(x) and lo = bf16(x - hi) (round to nearest
+// even), two values per conversion: hi of a pair is one v_cvt_pk_bf16_f32,
+// its two halves widen back to FP32 by a shift and a mask.
+__device__ __forceinline__ void split2(float a, float b, bf16x2 &h, bf16x2 &l)
+{
+    h = __builtin_convertvector(f32x2{a, b}, bf16x2);
+    const uint32_t u = __builtin_bit_cast(uint32_t, h);
+    const float ha = __uint_as_float(u << 16), hb = __uint_as_float(u & 0xffff0000u);
+    l = __builtin_convertvector(f32x2{a - ha, b - hb}, bf16x2);
+}
+
+// The split of the 8 K-slots of a slab made of two 16-row result tiles.
 __device__ __forceinline__ void split_bf16(const f32x4 lo4, const f32x4 hi4, bf16x8 &h, bf16x8 &l)
 {
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-        const float v = e < 4 ? lo4[e] : hi4[e - 4];
-        const __bf16 vh = (__bf16)v;
-        h[e] = vh;
-        l[e] = (__bf16)(v - (float)vh);
-    }
+    bf16x2 h0, h1, h2, h3, l0, l1, l2, l3;
+    split2(lo4[0], lo4[1], h0, l0);
+    split2(lo4[2], lo4[3], h1, l1);
+    split2(hi4[0], hi4[1], h2, l2);
+    split2(hi4[2], hi4[3], h3, l3);
+    h = bf16x8{h0[0], h0[1], h1[0], h1[1], h2[0], h2[1], h3[0], h3[1]};
+    l = bf16x8{l0[0], l0[1], l1[0], l1[1], l2[0], l2[1], l3[0], l3[1]};
 }
 
 __device__ __forceinline__ f32x4 mfma_bf16(bf16x8 a, bf16x8 b, f32x4 c)
