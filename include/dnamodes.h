@@ -252,6 +252,15 @@ int dm_get_tiling(const dm_ctx *ctx, double *out, size_t len, int32_t *n_buckets
 /* Text of the last autotuning (one line per timed tile shape), or "". */
 const char *dm_tuning_report(const dm_ctx *ctx);
 
+/* Model parameters of a coarse-grained chain (Sec. 7): one bead per k
+   basepairs, on the force-extension curve of Eq. (x1) with r = l_p / a and
+   y = l_p K_0 / kT (Eq. x2).  With r_k = r / k and y unchanged, Eq. (x4):
+       T*_k = (2 r^2 + k^2 y) r / (k^3 y^2),  nu_k = r^2 / (2 r^2 + k^2 y)
+   (k = 1 is the fit of Eq. x3).  The bond rest length of the reduced model
+   is b_k = 1/(1 - 2 nu_k) in units of d_k = k a / b_k.  Host only, no
+   context.  Errors: DM_EINVAL for r <= 0, y <= 0, k < 1 or NULL outputs. */
+int dm_coarse_grain(double r, double y, int32_t k, double *T_star_k, double *nu_k);
+
 /* Synchronise the context's stream. */
 int dm_sync(dm_ctx *ctx);
 

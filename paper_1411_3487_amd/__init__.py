@@ -5,7 +5,7 @@ The simulation runs in the HIP library libdnamodes.so (C ABI in
 include/dnamodes.h); this package holds the build script, a ctypes binding
 (``_lib``) and the seeded synthetic input generators (``inputs``).
 """
-from ._lib import (Context, DMError, load, DM_FP64, DM_FP32, DM_BF16X3,  # noqa: F401
+from ._lib import (Context, DMError, coarse_grain, load, DM_FP64, DM_FP32, DM_BF16X3,  # noqa: F401
                    DM_OBS_CHAIN, DM_OBS_MODES, DM_OBS_ACCUM, DM_OBS_RESET)
 
 # dsDNA in the paper's reduced units (Sec. 2a) and its maximal time steps

@@ -63,7 +63,7 @@ class dm_params(ctypes.Structure):
 EXPORTS = ["dm_init_chains", "dm_set_params", "dm_step_modes", "dm_step_euler", "dm_step_mc",
            "dm_observables", "dm_observables_size", "dm_get_positions", "dm_get_modes",
            "dm_save_state", "dm_load_state", "dm_get_step", "dm_get_tiling",
-           "dm_tuning_report", "dm_sync", "dm_destroy", "dm_last_error"]
+           "dm_tuning_report", "dm_coarse_grain", "dm_sync", "dm_destroy", "dm_last_error"]
 
 _lib = None
 
@@ -94,6 +94,8 @@ def load(path: str = LIB_PATH):
         "dm_get_step": ([vp, ctypes.POINTER(i64)], ctypes.c_int),
         "dm_get_tiling": ([vp, vp, sz, ctypes.POINTER(i32)], ctypes.c_int),
         "dm_tuning_report": ([vp], ctypes.c_char_p),
+        "dm_coarse_grain": ([ctypes.c_double, ctypes.c_double, i32, ctypes.POINTER(ctypes.c_double),
+                             ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
         "dm_sync": ([vp], ctypes.c_int),
         "dm_destroy": ([vp], ctypes.c_int),
         "dm_last_error": ([vp], ctypes.c_char_p),
@@ -104,6 +106,16 @@ def load(path: str = LIB_PATH):
         fn.restype = res
     _lib = lib
     return lib
+
+
+def coarse_grain(r: float, y: float, k: int):
+    """(T*_k, nu_k) of a chain with one bead per k basepairs (dm_coarse_grain)."""
+    lib = load()
+    t, n = ctypes.c_double(), ctypes.c_double()
+    rc = lib.dm_coarse_grain(r, y, k, ctypes.byref(t), ctypes.byref(n))
+    if rc != DM_OK:
+        raise DMError(rc, lib.dm_last_error(None).decode())
+    return t.value, n.value
 
 
 class Context:

@@ -864,6 +864,17 @@ int dm_get_tiling(const dm_ctx *ctx, double *out, size_t len, int32_t *n_buckets
 
 const char *dm_tuning_report(const dm_ctx *ctx) { return ctx ? ctx->tune_report.c_str() : ""; }
 
+int dm_coarse_grain(double r, double y, int32_t k, double *T_star_k, double *nu_k)
+{
+    if (!(r > 0.0) || !(y > 0.0) || k < 1 || !T_star_k || !nu_k || !std::isfinite(r) ||
+        !std::isfinite(y))
+        return fail(nullptr, DM_EINVAL, "coarse graining needs r > 0, y > 0, k >= 1");
+    const double kk = (double)k, a = 2.0 * r * r + kk * kk * y;
+    *T_star_k = a * r / (kk * kk * kk * y * y);
+    *nu_k = r * r / a;
+    return DM_OK;
+}
+
 const char *dm_last_error(const dm_ctx *ctx)
 {
     return ctx ? ctx->err.c_str() : g_init_error.c_str();

@@ -66,3 +66,18 @@ def test_null_pointers_are_rejected():
     assert lib.dm_init_chains(None, 1, b.ctypes.data, None, 0, 0, None) == _lib.DM_EINVAL
     assert lib.dm_step_modes(None, 1) == _lib.DM_EINVAL
     assert lib.dm_destroy(None) == _lib.DM_EINVAL
+
+
+def test_coarse_grain_reproduces_table3():
+    """Eqs. (x3), (x4) against the values Table 3 prints (r = l_p/a = 120,
+    y = l_p K_0/kT = 12000 reproduce its k = 1 row T* = 0.034, nu = 6/17)."""
+    rows = np.loadtxt(os.path.join(ROOT, "tests", "golden", "table3_coarse_grain.txt"))
+    for k, t_ref, nu_ref in rows:
+        t, nu = _lib.coarse_grain(120.0, 12000.0, int(k))
+        # printed to 3-4 significant digits (T*) and 3-6 (nu)
+        assert t == pytest.approx(t_ref, rel=2e-3), k
+        assert nu == pytest.approx(nu_ref, rel=1e-2 if k == 1 else 1e-5), k
+    t3, nu3 = _lib.coarse_grain(120.0, 12000.0, 3)
+    assert nu3 == pytest.approx(120.0 ** 2 / (2 * 120.0 ** 2 + 9 * 12000.0), rel=1e-14)
+    with pytest.raises(_lib.DMError):
+        _lib.coarse_grain(-1.0, 1.0, 1)

@@ -88,3 +88,30 @@ def test_mc_equilibrium_values_match_mode_dynamics():
         a, b = (q[s][key] / q[s]["n_samples"] for s in ("mc", "dyn"))
         print(f"{key}: MC {a:.5g}  dynamics {b:.5g}  ratio {b / a:.4f}")
         assert abs(b / a - 1) < 0.05, key
+
+
+def test_coarse_grained_chain_keeps_the_end_to_end_distance():
+    """Sec. 7: a 128-bp chain as 129 beads (k = 1) or as 65 beads of two
+    basepairs (k = 2) with the parameters of Eq. (x4) (r = 120, y = 12000):
+    Monte Carlo <L^2> in units of a^2 agree within 5 %, and both lie within
+    10 % of the wormlike-chain value 2 l_p L_c [1 - (l_p/L_c)(1 - e^{-L_c/l_p})]."""
+    r, y, B = 120.0, 12000.0, 256
+    L2 = {}
+    for k, M in ((1, 129), (2, 65)):
+        T, nu = _lib.coarse_grain(r, y, k)
+        b = 1.0 / (1.0 - 2.0 * nu)
+        pos = inputs.straight_chains(B, M, b, seed=30 + k, random_orientation=True)
+        with Context(pos, seed=40 + k, precision="fp64") as ctx:
+            ctx.set_params([M], [1.0], T_star=T, nu=nu, sample_every=20)
+            ctx.step_mc(6000)
+            ctx.accumulators(reset=True)
+            ctx.step_mc(12000)
+            a = ctx.accumulators()[0]
+        d = k / b                      # reduced length unit in basepairs
+        L2[k] = a["L2"] / a["n_samples"] / B * d * d
+    Lc, lp = 128.0, r
+    wlc = 2 * lp * Lc * (1 - lp / Lc * (1 - np.exp(-Lc / lp)))
+    print(f"<L^2>/a^2: k=1 {L2[1]:.1f}, k=2 {L2[2]:.1f}, wormlike chain {wlc:.1f}")
+    assert abs(L2[2] / L2[1] - 1) < 0.05
+    for k in (1, 2):
+        assert abs(L2[k] / wlc - 1) < 0.10
