@@ -92,7 +92,13 @@ extern "C" {
    vector (L_x, L_y) is "along +x" once L_x > |(L_x, L_y)|/2 and "along -x"
    once L_x < -|(L_x, L_y)|/2 (hysteresis: in between the previous state is
    kept); each change between the two states at a sample is one tumble, and
-   a tumbling time is the interval between two tumbles of a chain. */
+   a tumbling time is the interval between two tumbles of a chain.
+   Then DM_NCORR blocks of 4 doubles, one per lag l_j (l_0 = 0,
+   l_j = 2^(j-1) samples), for the time correlations of Sec. 6 (measured
+   for j < corr_lags, zero otherwise): sum of L(t).L(t - l_j) (end-to-end
+   vector), of u_m(t).u_m(t - l_j) (middle bond u_{M/2}), of
+   |d(t) - d(t - l_j)|^2 with d = r_{(M-1)/2} - r_cm (msd of the middle bead
+   about the centre of mass), and the number of pairs summed. */
 #define DM_NACC_HEAD    13
 #define DM_ACC_M         0  /* beads per chain in this bucket */
 #define DM_ACC_NCHAINS   1
@@ -108,6 +114,11 @@ extern "C" {
 #define DM_ACC_TAU2     11  /* sum of squared tumbling times (steps^2) */
 #define DM_ACC_NTAU     12  /* number of tumbling times */
 #define DM_NTUMBLE_BINS 32
+#define DM_NCORR        16
+#define DM_CORR_L        0  /* offsets inside one lag block */
+#define DM_CORR_UMID     1
+#define DM_CORR_MSD      2
+#define DM_CORR_COUNT    3
 
 /* dm_get_tiling(): DM_NTILING doubles per length bucket. */
 #define DM_NTILING       8
@@ -158,6 +169,11 @@ typedef struct {
                                 where that form exists for the length (it
                                 overrides the autotuner); results do not
                                 depend on the tile shape */
+    int32_t corr_lags;       /* 0..14: number of lags of the time
+                                correlations in the accumulators (a ring of
+                                2^(corr_lags-1) past samples per chain is
+                                kept on the device; 0 = off).  The ring
+                                restarts at dm_set_params and dm_load_state */
 } dm_params;
 
 /* Create a context for n_chains chains; beads[c] >= 2 is the number of beads

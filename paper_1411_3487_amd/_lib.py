@@ -33,6 +33,7 @@ DM_OBS_RESET = 8
 DM_NCHAIN_OBS = 16
 DM_NACC_HEAD = 13
 DM_NTUMBLE_BINS = 32
+DM_NCORR = 16
 CHAIN_OBS_NAMES = ["bond_mean", "L2", "Lx", "Ly", "Lz", "cmx", "cmy", "cmz",
                    "umx", "umy", "umz", "dmx", "dmy", "dmz", "xspan", "bond2_mean"]
 ACC_NAMES = ["M", "n_chains", "n_samples", "bond", "bond2", "L2", "msd_cm", "dmid2", "xspan",
@@ -57,7 +58,8 @@ class dm_params(ctypes.Structure):
                 ("dt", ctypes.POINTER(ctypes.c_double)),
                 ("sample_every", ctypes.c_int32), ("check_finite", ctypes.c_int32),
                 ("autotune", ctypes.c_int32), ("use_graphs", ctypes.c_int32),
-                ("tiles_per_wg", ctypes.c_int32), ("table_mode", ctypes.c_int32)]
+                ("tiles_per_wg", ctypes.c_int32), ("table_mode", ctypes.c_int32),
+                ("corr_lags", ctypes.c_int32)]
 
 
 EXPORTS = ["dm_init_chains", "dm_set_params", "dm_step_modes", "dm_step_euler", "dm_step_mc",
@@ -171,7 +173,7 @@ class Context:
     # ------------------------------------------------------------------ API
     def set_params(self, lengths, dt, T_star=None, nu=None, gamma_dot=0.0, nonlinear=True,
                    sample_every=0, check_finite=False, physical=None, autotune=False,
-                   use_graphs=False, tiles_per_wg=0, table_mode=0):
+                   use_graphs=False, tiles_per_wg=0, table_mode=0, corr_lags=0):
         """Reduced units by default; physical=dict(lambda_, kappa, kT, a, xi)."""
         p = dm_params()
         if physical:
@@ -191,6 +193,7 @@ class Context:
         p.autotune = 1 if autotune else 0
         p.use_graphs = 1 if use_graphs else 0
         p.tiles_per_wg = tiles_per_wg
+        p.corr_lags = corr_lags
         p.table_mode = {"auto": 0, "resident": 1, "streamed": 2}.get(table_mode, table_mode)
         self._check(self.lib.dm_set_params(self.h, ctypes.byref(p)))
 
@@ -233,7 +236,9 @@ class Context:
 
     def accumulators(self, reset=False) -> list:
         """Per length bucket: dict of the head sums, 'modes' (sum |R_p|^2) and
-        'tumble_hist' (counts of tumbling times in octaves of steps)."""
+        'tumble_hist' (counts of tumbling times in octaves of steps) and 'corr'
+        (DM_NCORR x 4: per lag 0, 1, 2, 4, ... samples the sums of L.L', u_m.u_m',
+        |d - d'|^2 and the pair count)."""
         flat = self.observables(DM_OBS_ACCUM | (DM_OBS_RESET if reset else 0))
         out, i = [], 0
         while i < flat.size:
@@ -242,8 +247,10 @@ class Context:
             j = i + DM_NACC_HEAD
             d["modes"] = flat[j:j + M].copy()
             d["tumble_hist"] = flat[j + M:j + M + DM_NTUMBLE_BINS].copy()
+            c0 = j + M + DM_NTUMBLE_BINS
+            d["corr"] = flat[c0:c0 + 4 * DM_NCORR].reshape(DM_NCORR, 4).copy()
             out.append(d)
-            i = j + M + DM_NTUMBLE_BINS
+            i = c0 + 4 * DM_NCORR
         return out
 
     def _split(self, flat):

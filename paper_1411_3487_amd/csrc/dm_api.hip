@@ -41,6 +41,8 @@ struct Bucket {
     double *d_acc = nullptr;         // n*acc_width(M)
     double *d_accsum = nullptr;      // acc_width(M)
     double *d_tumble = nullptr;      // 2n: tumbling state, step of the last tumble + 1
+    double *d_ring = nullptr;        // n * 2^(K-1) * 9: past (L, u_m, d) for the correlations
+    double *d_ccount = nullptr;      // n: samples written to the ring
     // Metropolis sampler (allocated on first use)
     double *d_chiT = nullptr;        // chi_{n,p} at [p][n-1], M x (M-1)
     double *d_mcstep = nullptr;      // proposal half-widths s_p
@@ -71,7 +73,7 @@ struct dm_ctx {
     // fused paths: one launch over all buckets, and the captured graph of
     // one sampling block (fused launch, step-counter advance, observables)
     dm::FusedPlan plan;
-    int use_graphs = 0, autotune = 0;
+    int use_graphs = 0, autotune = 0, corr_lags = 0;
     int64_t *d_step = nullptr;
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
@@ -122,7 +124,7 @@ void free_bucket(Bucket &b)
     void *ptrs[] = {b.d_ids, b.d_off,  b.d_Ainv, b.d_Apos, b.d_Afwd, b.d_E,   b.d_C,
                     b.d_W,   b.d_R64, b.d_r,    b.d_F,    b.d_dH,   b.d_obs, b.d_m2,
                     b.d_acc, b.d_accsum, b.d_cm0, b.d_tumble, b.d_chiT, b.d_mcstep,
-                    b.d_mcacc};
+                    b.d_mcacc, b.d_ring, b.d_ccount};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     dm::fused_free(b.fused);
@@ -148,15 +150,15 @@ int observe(dm_ctx *ctx, int accumulate, hipStream_t st, bool captured = false)
     for (Bucket &b : ctx->buckets) {
         if (fused_precision(ctx->precision)) {
             DM_HIP(ctx, dm::fused_observe(b.fused, b.M, b.d_obs, b.d_m2, b.d_acc, b.d_cm0,
-                                          b.d_tumble, b.d_tumble + b.n, ctx->d_step, accumulate,
-                                          st));
+                                          b.d_tumble, b.d_tumble + b.n, ctx->d_step, b.d_ring,
+                                          b.d_ccount, ctx->corr_lags, accumulate, st));
             continue;
         }
         int rc = bucket_positions(ctx, b, st);
         if (rc) return rc;
         DM_HIP(ctx, dm::launch_chain_obs(b.d_r, b.d_R64, b.d_obs, b.d_m2, b.d_acc, b.d_cm0,
-                                         b.d_tumble, b.d_tumble + b.n, ctx->d_step, b.M, b.n,
-                                         accumulate, st));
+                                         b.d_tumble, b.d_tumble + b.n, ctx->d_step, b.d_ring,
+                                         b.d_ccount, ctx->corr_lags, b.M, b.n, accumulate, st));
     }
     return DM_OK;
 }
@@ -403,6 +405,8 @@ int dm_set_params(dm_ctx *ctx, const dm_params *p)
     if (p->sample_every < 0) return fail(ctx, DM_EINVAL, "sample_every must be >= 0");
     if (p->tiles_per_wg < 0 || p->tiles_per_wg > 4 || p->table_mode < 0 || p->table_mode > 2)
         return fail(ctx, DM_EINVAL, "tiles_per_wg must be 0..4 and table_mode 0..2");
+    if (p->corr_lags < 0 || p->corr_lags > 14)
+        return fail(ctx, DM_EINVAL, "corr_lags must be 0..14");
     std::vector<double> dtau(ctx->buckets.size());
     for (size_t i = 0; i < ctx->buckets.size(); ++i) {
         int found = -1;
@@ -442,6 +446,23 @@ int dm_set_params(dm_ctx *ctx, const dm_params *p)
     ctx->sample_every = p->sample_every;
     ctx->check_finite = p->check_finite ? 1 : 0;
     ctx->use_graphs = p->use_graphs ? 1 : 0;
+    {   // correlation rings: (re)allocate for the lag count, restart
+        const int K = p->corr_lags;
+        for (Bucket &b : ctx->buckets) {
+            if (b.d_ring) (void)hipFree(b.d_ring);
+            b.d_ring = nullptr;
+            if (!b.d_ccount) {
+                int rc = dalloc(ctx, &b.d_ccount, b.n);
+                if (rc) return rc;
+            }
+            DM_HIP(ctx, hipMemsetAsync(b.d_ccount, 0, sizeof(double) * b.n, ctx->stream));
+            if (K > 0) {
+                int rc = dalloc(ctx, &b.d_ring, (size_t)b.n * 9 * ((size_t)1 << (K - 1)));
+                if (rc) return rc;
+            }
+        }
+        ctx->corr_lags = K;
+    }
     ctx->autotune = p->autotune ? 1 : 0;
     drop_graph(ctx);  // captured launches hold the old tables and plan
     if (fused_precision(ctx->precision)) {
@@ -804,6 +825,9 @@ int dm_load_state(dm_ctx *ctx, const void *buf, size_t len)
             DM_HIP(ctx, dm::fused_pack_modes(b.fused, b.d_R64, b.M, b.n, ctx->stream));
         p += s1 + s2 + s3 + s4;
     }
+    for (Bucket &b : ctx->buckets)  // the correlation rings restart
+        if (b.d_ccount)
+            DM_HIP(ctx, hipMemsetAsync(b.d_ccount, 0, sizeof(double) * b.n, ctx->stream));
     DM_HIP(ctx, hipStreamSynchronize(ctx->stream));
     ctx->step = h.step;
     return DM_OK;

@@ -72,7 +72,8 @@ hipError_t fused_advance_step(int64_t *d_step, int64_t n, hipStream_t st);
 // the fused state directly (positions in FP32 MFMA, sums in FP64).
 hipError_t fused_observe(const FusedBucket &f, int M, double *obs, double *m2, double *acc,
                          const double *cm0, double *tstate, double *tlast,
-                         const int64_t *d_step, int accumulate, hipStream_t st);
+                         const int64_t *d_step, double *ring, double *ccount, int K,
+                         int accumulate, hipStream_t st);
 hipError_t fused_check_finite(const FusedBucket &f, int M, int n, int *flag, hipStream_t st);
 
 }  // namespace dm

@@ -609,7 +609,8 @@ struct ObsArgs {
     const double *cm0;
     double *tstate, *tlast;
     const int64_t *step;
-    int M, n, accumulate;
+    double *ring, *ccount;
+    int K, M, n, accumulate;
 };
 
 template <int RT>
@@ -755,6 +756,12 @@ __global__ __launch_bounds__(256) void fused_obs_kernel(ObsArgs a)
         a.tlast[c] = k + 1.0;
     }
     a.tstate[c] = s1;
+    if (a.K > 0) {
+        const double v[9] = {Lx, Ly, Lz, o[DM_CO_UMID], o[DM_CO_UMID + 1], o[DM_CO_UMID + 2],
+                             o[DM_CO_DMID], o[DM_CO_DMID + 1], o[DM_CO_DMID + 2]};
+        corr_update(a.ring + c * ((size_t)9 << (a.K - 1)), a.ccount + c,
+                    ac + DM_NACC_HEAD + M + DM_NTUMBLE_BINS, v, a.K);
+    }
 }
 
 // FP64 amplitudes [chain][component][p] -> fused state (even modes scaled
@@ -1346,7 +1353,8 @@ static void launch_obs(const ObsArgs &a, int ntiles, hipStream_t st)
 
 hipError_t fused_observe(const FusedBucket &f, int M, double *obs, double *m2, double *acc,
                          const double *cm0, double *tstate, double *tlast,
-                         const int64_t *d_step, int accumulate, hipStream_t st)
+                         const int64_t *d_step, double *ring, double *ccount, int K,
+                         int accumulate, hipStream_t st)
 {
     if (f.n <= 0) return hipSuccess;
     ObsArgs a;
@@ -1361,6 +1369,9 @@ hipError_t fused_observe(const FusedBucket &f, int M, double *obs, double *m2, d
     a.tstate = tstate;
     a.tlast = tlast;
     a.step = d_step;
+    a.ring = ring;
+    a.ccount = ccount;
+    a.K = K;
     a.M = M;
     a.n = f.n;
     a.accumulate = accumulate;

@@ -8,7 +8,35 @@
 namespace dm {
 
 // Doubles of one chain's accumulators: head, |R_p|^2 sums, tumbling bins.
-__host__ __device__ inline int acc_width(int M) { return DM_NACC_HEAD + M + DM_NTUMBLE_BINS; }
+__host__ __device__ inline int acc_width(int M)
+{
+    return DM_NACC_HEAD + M + DM_NTUMBLE_BINS + 4 * DM_NCORR;
+}
+
+// Time correlations at one sample of one chain: v = (L, u_m, d), 9 doubles;
+// ring holds the chain's last R = 2^(K-1) samples (K >= 1 lags), count the
+// samples written so far; the lag blocks of the chain's accumulators start
+// at corr.  Lag j compares with the sample l_j = (j ? 2^(j-1) : 0) back.
+__device__ inline void corr_update(double *ring, double *count, double *corr, const double v[9],
+                                   int K)
+{
+    const long R = 1L << (K - 1);
+    const long i = (long)*count;
+    double *slot = ring + (i & (R - 1)) * 9;
+    for (int q = 0; q < 9; ++q) slot[q] = v[q];
+    for (int j = 0; j < K; ++j) {
+        const long l = j ? (1L << (j - 1)) : 0;
+        if (l > i) break;
+        const double *w = ring + ((i - l) & (R - 1)) * 9;
+        double *cj = corr + 4 * j;
+        cj[DM_CORR_L] += v[0] * w[0] + v[1] * w[1] + v[2] * w[2];
+        cj[DM_CORR_UMID] += v[3] * w[3] + v[4] * w[4] + v[5] * w[5];
+        const double dx = v[6] - w[6], dy = v[7] - w[7], dz = v[8] - w[8];
+        cj[DM_CORR_MSD] += dx * dx + dy * dy + dz * dz;
+        cj[DM_CORR_COUNT] += 1.0;
+    }
+    *count = (double)(i + 1);
+}
 
 // Plain-form (FP64) kernels, dm_plain.hip.  Every launcher only enqueues on
 // `st` and returns the launch status.
@@ -50,11 +78,13 @@ hipError_t launch_mc(double *R, const double *chiT, const double *sstep, const i
 // acc[c*acc_width(M) + .] when accumulate != 0, advancing the tumbling state
 // (tstate[c] = -1, 0, +1; tlast[c] = step of the last tumble + 1, or 0) with
 // the current step *step_dev.
+// With K > 0 lags also the time correlations (corr_update) with the ring
+// ring[c*R*9] and the sample counts ccount[c].
 hipError_t launch_chain_obs(const double *pos, const double *R, double *obs,
                             double *m2, double *acc, const double *cm0,
                             double *tstate, double *tlast,
-                            const int64_t *step_dev, int M, int nch,
-                            int accumulate, hipStream_t st);
+                            const int64_t *step_dev, double *ring, double *ccount,
+                            int K, int M, int nch, int accumulate, hipStream_t st);
 
 // out[j] = sum_c acc[c*width + j], summed over chains in order.
 hipError_t launch_reduce_chains(const double *acc, double *out, int width,

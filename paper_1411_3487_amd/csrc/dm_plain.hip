@@ -266,6 +266,8 @@ __global__ __launch_bounds__(64) void chain_obs_kernel(const double *__restrict_
                                                        double *__restrict__ tstate,
                                                        double *__restrict__ tlast,
                                                        const int64_t *__restrict__ step_dev,
+                                                       double *__restrict__ ring,
+                                                       double *__restrict__ ccount, int K,
                                                        int M, int accumulate)
 {
     const int c = blockIdx.x, lane = threadIdx.x;
@@ -348,6 +350,11 @@ __global__ __launch_bounds__(64) void chain_obs_kernel(const double *__restrict_
                 tlast[c] = k + 1.0;
             }
             tstate[c] = s1;
+            if (K > 0) {
+                const double v[9] = {Lx, Ly, Lz, o[8], o[9], o[10], o[11], o[12], o[13]};
+                corr_update(ring + (size_t)c * ((size_t)9 << (K - 1)), ccount + c,
+                            accc + DM_NACC_HEAD + M + DM_NTUMBLE_BINS, v, K);
+            }
         }
     }
 }
@@ -519,12 +526,12 @@ hipError_t launch_mc(double *R, const double *chiT, const double *sstep, const i
 
 hipError_t launch_chain_obs(const double *pos, const double *R, double *obs, double *m2,
                             double *acc, const double *cm0, double *tstate, double *tlast,
-                            const int64_t *step_dev, int M, int nch, int accumulate,
-                            hipStream_t st)
+                            const int64_t *step_dev, double *ring, double *ccount, int K, int M,
+                            int nch, int accumulate, hipStream_t st)
 {
     if (nch == 0) return hipSuccess;
     hipLaunchKernelGGL(chain_obs_kernel, dim3(nch), dim3(64), 0, st, pos, R, obs, m2, acc, cm0,
-                       tstate, tlast, step_dev, M, accumulate);
+                       tstate, tlast, step_dev, ring, ccount, K, M, accumulate);
     return hipGetLastError();
 }
 

@@ -34,15 +34,15 @@ def test_header_constants_match_binding():
     for name in ["DM_OK", "DM_EINVAL", "DM_ENOMEM", "DM_EHIP", "DM_ENONFINITE", "DM_ESTATE",
                  "DM_FP64", "DM_FP32", "DM_BF16X3", "DM_OBS_CHAIN", "DM_OBS_MODES",
                  "DM_OBS_ACCUM", "DM_OBS_RESET", "DM_NCHAIN_OBS", "DM_NACC_HEAD",
-                 "DM_NTILING", "DM_NTUMBLE_BINS"]:
+                 "DM_NTILING", "DM_NTUMBLE_BINS", "DM_NCORR"]:
         assert int(consts[name]) == getattr(_lib, name), name
     assert len(_lib.CHAIN_OBS_NAMES) == _lib.DM_NCHAIN_OBS
     assert len(_lib.ACC_NAMES) == _lib.DM_NACC_HEAD
 
 
 def test_params_struct_layout():
-    # 8 doubles, 2 int32, 2 pointers, 6 int32 (natural alignment, x86-64)
-    assert ctypes.sizeof(_lib.dm_params) == 8 * 8 + 8 + 16 + 24
+    # 8 doubles, 2 int32, 2 pointers, 7 int32, padded to 8 (x86-64)
+    assert ctypes.sizeof(_lib.dm_params) == 8 * 8 + 8 + 16 + 28 + 4
 
 
 @pytest.mark.parametrize("n,beads,prec", [(0, [64], 0), (1, [1], 0), (1, [64], 7),

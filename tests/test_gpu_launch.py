@@ -88,7 +88,7 @@ def test_graph_replays_match_eager(prec):
     for graphs in (False, True):
         c = Context(chains, seed=2, precision=prec)
         c.set_params(LENS, [DTAU[m] for m in LENS], T_star=TS, nu=NU, sample_every=10,
-                     use_graphs=graphs)
+                     use_graphs=graphs, corr_lags=4)
         ctxs.append(c)
     try:
         total = 0
@@ -105,6 +105,7 @@ def test_graph_replays_match_eager(prec):
                 for k in ("bond", "L2", "msd_cm"):
                     assert x[k] == y[k], (n, k)
                 assert np.array_equal(x["modes"], y["modes"])
+                assert np.array_equal(x["corr"], y["corr"])
             assert ctxs[0].step == ctxs[1].step
     finally:
         for c in ctxs:
