@@ -27,7 +27,7 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--workload", default="modes",
-                    choices=["modes", "uneven", "shear", "mc", "dtmax"],
+                    choices=["modes", "uneven", "shear", "mc", "dtmax", "dtmax_t"],
                     help="modes: 4096 x 256 bp (the headline line); uneven: 8192 chains of "
                          "64..512 bp in one launch; shear: 2048 x 256 bp under simple shear "
                          "at Wi = 1, 10, 100 (tumbling and extension, FP32 vs FP64); mc: "
@@ -323,8 +323,96 @@ def dtmax_workload(args):
                       "results": out}))
 
 
+def dtmax_t_workload(args):
+    """Dynamical group of the time-step test (Sec. 6): the time correlations
+    Q(t) (end-to-end vector, middle bond: autocorrelations; middle bead about
+    the centre of mass: msd) at several time steps, from Monte Carlo
+    equilibrated chains.  At fixed times tau the effective decay constant
+    Q~ = (1/Q) dQ/dtau (central differences over the power-of-two lags) is
+    divided by its value at the smallest time step; the paper accepts a time
+    step while these ratios stay within 10 %.  Autocorrelations that have
+    decayed below 5 % of their start are left out (noise)."""
+    import numpy as np
+    import torch
+    from paper_1411_3487_amd import Context, inputs, NU_DSDNA, T_STAR_DSDNA
+    torch.cuda.set_device(0)
+    b = 1.0 / (1.0 - 2.0 * NU_DSDNA)
+    B, K = 1024, 14
+    # M: (time steps, sampling interval in tau, run length in tau, test times,
+    #     Monte Carlo burn-in sweeps)
+    plan = {64: ([0.1, 1, 10, 20, 50, 100], 100.0, 2.0e6, [100, 1e3, 1e4, 1e5], 3000),
+            128: ([1, 10, 50, 100, 200], 1000.0, 2.0e7, [1e3, 1e4, 1e5, 1e6], 8000),
+            256: ([10, 100, 200, 500], 1.0e4, 1.0e8, [1e4, 1e5, 1e6, 1e7], 20000)}
+    names = ("L", "umid", "msd")
+    out = []
+    for M, (dts, ts, run, times, burn) in plan.items():
+        pos = inputs.straight_chains(B, M, b, seed=M, random_orientation=True)
+        mc = Context(pos, seed=M, precision="fp64")
+        mc.set_params([M], [1.0], T_star=T_STAR_DSDNA, nu=NU_DSDNA)
+        mc.step_mc(burn)
+        state = mc.positions()
+        mc.close()
+        lags = np.array([0.0] + [ts * 2 ** (j - 1) for j in range(1, K)])
+        curves = {}
+        for dt in dts:
+            se = int(round(ts / dt))
+            n = int(round(run / dt))
+            t0 = time.perf_counter()
+            ctx = Context(state, seed=M + 2, precision=args.precision)
+            ctx.set_params([M], [float(dt)], T_star=T_STAR_DSDNA, nu=NU_DSDNA,
+                           sample_every=se, corr_lags=K, use_graphs=True)
+            ctx.step_modes(n)
+            c = ctx.accumulators()[0]["corr"][:K]
+            ctx.close()
+            q = c[:, :3] / np.maximum(c[:, 3:4], 1)
+            curves[dt] = q
+            print(f"# M={M} dtau={dt}: {n} steps, {time.perf_counter() - t0:.0f} s",
+                  file=sys.stderr, flush=True)
+        ref = curves[dts[0]]
+
+        def decay(q, i, t):
+            # d ln Q / d tau at lag t by a central difference on the lag grid
+            j = int(np.argmin(np.abs(lags - t)))
+            j = min(max(j, 1), K - 2)
+            lo, hi = q[j - 1, i], q[j + 1, i]
+            if lo <= 0 or hi <= 0:
+                return None, lags[j]
+            return (np.log(hi) - np.log(lo)) / (lags[j + 1] - lags[j - 1]), lags[j]
+        rows = []
+        for dt in dts[1:]:
+            ratios, ok = {}, True
+            for i, name in enumerate(names):
+                for t in times:
+                    j = int(np.argmin(np.abs(lags - t)))
+                    if i < 2 and (ref[j, i] < 0.05 * ref[0, i]):
+                        continue                       # decayed: noise only
+                    qa, tt = decay(curves[dt], i, t)
+                    qb, _ = decay(ref, i, t)
+                    if qa is None or qb is None or qb == 0:
+                        continue
+                    r = qa / qb
+                    ratios[f"{name}@{tt:g}"] = r
+                    ok = ok and abs(r - 1) <= 0.10
+            rows.append({"dtau": dt, "ratios": ratios, "within_10pct": ok})
+            print(f"# M={M} dtau={dt}: ok={ok} {ratios}", file=sys.stderr, flush=True)
+        passed = []
+        for r in rows:
+            if not r["within_10pct"]:
+                break
+            passed.append(r["dtau"])
+        out.append({"M": M, "N": M - 1, "dtau_min": dts[0], "runs": rows,
+                    "lags_tau": lags.tolist(),
+                    "Q_ref": {n: ref[:, i].tolist() for i, n in enumerate(names)},
+                    "dtau_max_from_Qt": passed[-1] if passed else dts[0]})
+    print(json.dumps({"workload": f"dtau_max from time correlations, {B} chains per length, "
+                                  f"{args.precision} mode dynamics",
+                      "results": out}))
+
+
 def main():
     args = parse()
+    if args.workload == "dtmax_t" and args.gpus == 1:
+        return dtmax_t_workload(args)
     if args.workload == "mc" and args.gpus == 1:
         return mc_workload(args)
     if args.workload == "dtmax" and args.gpus == 1:

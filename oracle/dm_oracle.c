@@ -378,6 +378,138 @@ double orc_energy(int M, double nu, const double *pos)
 }
 
 /* ------------------------------------------------------------------------ */
+/* The nu -> 0 limit (Sec. 5c, Eqs. y2-y14): the inextensible wormlike      */
+/* chain in the bending time scale tau-bar = nu tau, T-bar = T* / nu, with   */
+/* Hamiltonian -sum_n u_n . u_{n+1} and bonds of unit length kept by the     */
+/* tensions f_n.  One step of length dt moves bead n by                      */
+/*   dr_n = (-f_n u_n + f_{n+1} u_{n+1} + h_{n+1} - h_n) dt                  */
+/*          + sqrt(2 T-bar dt) eta_n                                         */
+/* (Eq. y8) with h_n = -(u_{n-1} + u_{n+1}) the bending gradient on bond n;  */
+/* tension and bending act along the midpoint bonds                          */
+/* u^m_n = (u_n + u'_n)/|u_n + u'_n| (Eq. y14), and the f_n solve the        */
+/* tridiagonal system that keeps |u'_n| = |u_n| (Eqs. y11-y13):              */
+/*   (u_n + u'_n) . du_n = 0,                                                */
+/*   du_n = (f_{n-1} u^m_{n-1} - 2 f_n u^m_n + f_{n+1} u^m_{n+1}) dt + D_n,   */
+/* D_n the regular part of dr_n - dr_{n-1}.  Starting from u' = u the cycle  */
+/* (midpoint, forces, tensions, u') is repeated `iters` times.  Bonds are    */
+/* numbered n = 1..N (N = M - 1); f, h, u vanish outside.  Noise: the Euler  */
+/* convention with tag 3.  pos is 3*M per chain; only the bonds and bead 0   */
+/* are advanced, and the positions rebuilt from them.                       */
+/* ------------------------------------------------------------------------ */
+static void wlc_solve(int N, const double *a, const double *b, const double *c,
+                      const double *r, double *x, double *cp, double *dp)
+{
+    /* Thomas algorithm: a_n x_{n-1} + b_n x_n + c_n x_{n+1} = r_n, n < N */
+    cp[0] = c[0] / b[0];
+    dp[0] = r[0] / b[0];
+    for (int n = 1; n < N; ++n) {
+        const double m = b[n] - a[n] * cp[n - 1];
+        cp[n] = c[n] / m;
+        dp[n] = (r[n] - a[n] * dp[n - 1]) / m;
+    }
+    x[N - 1] = dp[N - 1];
+    for (int n = N - 2; n >= 0; --n) x[n] = dp[n] - cp[n] * x[n + 1];
+}
+
+void orc_step_wlc(int M, int n_chains, const uint32_t *chain_id, double *pos,
+                  double T_bar, double dt, int iters, uint64_t seed,
+                  int64_t step0, int64_t n_steps)
+{
+    const int N = M - 1;
+    const double amp = sqrt(2.0 * T_bar * dt);
+#pragma omp parallel
+    {
+        /* bonds u[n][a], n = 0..N+1 with u[0] = u[N+1] = 0 (bond n = 1..N) */
+        double *u = calloc((size_t)3 * (N + 2), sizeof(double));
+        double *un = calloc((size_t)3 * (N + 2), sizeof(double));
+        double *um = calloc((size_t)3 * (N + 2), sizeof(double));
+        double *w = calloc((size_t)3 * (N + 2), sizeof(double));
+        double *h = calloc((size_t)3 * (N + 2), sizeof(double));
+        double *dr = calloc((size_t)3 * (N + 1), sizeof(double));
+        double *eta = calloc((size_t)3 * (N + 1), sizeof(double));
+        double *D = calloc((size_t)3 * (N + 2), sizeof(double));
+        double *f = calloc((size_t)(N + 2), sizeof(double));
+        double *A = malloc(sizeof(double) * N), *Bd = malloc(sizeof(double) * N);
+        double *Cd = malloc(sizeof(double) * N), *Rr = malloc(sizeof(double) * N);
+        double *X = malloc(sizeof(double) * N), *cp = malloc(sizeof(double) * N);
+        double *dp = malloc(sizeof(double) * N);
+#pragma omp for schedule(dynamic, 1)
+        for (int c = 0; c < n_chains; ++c) {
+            double *x = pos + (size_t)c * 3 * M;
+            for (int n = 1; n <= N; ++n)
+                for (int a = 0; a < 3; ++a) u[3 * n + a] = x[a * M + n] - x[a * M + n - 1];
+            double r0[3] = {x[0], x[M], x[2 * M]};
+            for (int64_t k = step0; k < step0 + n_steps; ++k) {
+                for (int a = 0; a < 3; ++a)
+                    for (int n = 0; n <= N; ++n)
+                        eta[3 * n + a] = orc_normal(seed, (uint32_t)n, chain_id[c], k,
+                                                    (uint32_t)a, 3u);
+                memcpy(un, u, sizeof(double) * 3 * (N + 2));
+                for (int it = 0; it < iters; ++it) {
+                    /* midpoint bonds and the constraint weights */
+                    for (int n = 1; n <= N; ++n) {
+                        double s2 = 0.0;
+                        for (int a = 0; a < 3; ++a) {
+                            w[3 * n + a] = u[3 * n + a] + un[3 * n + a];
+                            s2 += w[3 * n + a] * w[3 * n + a];
+                        }
+                        for (int a = 0; a < 3; ++a) um[3 * n + a] = w[3 * n + a] / sqrt(s2);
+                    }
+                    /* bending gradient on each bond, at the midpoint */
+                    for (int n = 1; n <= N; ++n)
+                        for (int a = 0; a < 3; ++a)
+                            h[3 * n + a] = -(um[3 * (n - 1) + a] + um[3 * (n + 1) + a]);
+                    /* regular bead displacements and their bond differences */
+                    for (int n = 0; n <= N; ++n)
+                        for (int a = 0; a < 3; ++a) {
+                            const double hn = n >= 1 ? h[3 * n + a] : 0.0;
+                            const double hn1 = n + 1 <= N ? h[3 * (n + 1) + a] : 0.0;
+                            dr[3 * n + a] = (hn1 - hn) * dt + amp * eta[3 * n + a];
+                        }
+                    for (int n = 1; n <= N; ++n)
+                        for (int a = 0; a < 3; ++a)
+                            D[3 * n + a] = dr[3 * n + a] - dr[3 * (n - 1) + a];
+                    /* tensions: w_n . (f_{n-1} um_{n-1} - 2 f_n um_n + f_{n+1} um_{n+1}) dt
+                       = -w_n . D_n */
+                    for (int n = 1; n <= N; ++n) {
+                        double wl = 0.0, wm = 0.0, wr = 0.0, wd = 0.0;
+                        for (int a = 0; a < 3; ++a) {
+                            wl += w[3 * n + a] * um[3 * (n - 1) + a];
+                            wm += w[3 * n + a] * um[3 * n + a];
+                            wr += w[3 * n + a] * um[3 * (n + 1) + a];
+                            wd += w[3 * n + a] * D[3 * n + a];
+                        }
+                        A[n - 1] = wl * dt;
+                        Bd[n - 1] = -2.0 * wm * dt;
+                        Cd[n - 1] = wr * dt;
+                        Rr[n - 1] = -wd;
+                    }
+                    wlc_solve(N, A, Bd, Cd, Rr, X, cp, dp);
+                    f[0] = f[N + 1] = 0.0;
+                    for (int n = 1; n <= N; ++n) f[n] = X[n - 1];
+                    for (int n = 1; n <= N; ++n)
+                        for (int a = 0; a < 3; ++a)
+                            un[3 * n + a] = u[3 * n + a] + D[3 * n + a] +
+                                            (f[n - 1] * um[3 * (n - 1) + a] -
+                                             2.0 * f[n] * um[3 * n + a] +
+                                             f[n + 1] * um[3 * (n + 1) + a]) * dt;
+                }
+                /* bead 0 moves with its own tension, bending and noise */
+                for (int a = 0; a < 3; ++a)
+                    r0[a] += dr[a] + (N >= 1 ? f[1] * um[3 + a] * dt : 0.0);
+                memcpy(u, un, sizeof(double) * 3 * (N + 2));
+            }
+            for (int a = 0; a < 3; ++a) {
+                x[a * M] = r0[a];
+                for (int n = 1; n <= N; ++n) x[a * M + n] = x[a * M + n - 1] + u[3 * n + a];
+            }
+        }
+        free(u); free(un); free(um); free(w); free(h); free(dr); free(eta); free(D);
+        free(f); free(A); free(Bd); free(Cd); free(Rr); free(X); free(cp); free(dp);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
 /* Metropolis Monte Carlo in the mode representation, the paper's           */
 /* equilibrium benchmark (Sec. 6: "large MC steps in the slow modes and     */
 /* small steps in the fast modes").  The paper gives no more detail; this   */

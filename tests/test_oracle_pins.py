@@ -593,3 +593,71 @@ def test_mc_sweep_is_reproducible_and_keeps_the_centre_of_mass():
     assert np.all((acc_a > 0.4 * 20 * 45) & (acc_a < 0.75 * 20 * 45))
     still, acc0 = oracle.mc_sweeps(R, NU, TSTAR, 0.0, 5, seed=4)
     assert np.array_equal(still, R) and np.all(acc0 == 5 * 45)
+
+
+# ------------------------------------------- nu -> 0: inextensible WLC limit
+def _unit_chains(B, M, seed):
+    rng = np.random.default_rng(seed)
+    u = rng.standard_normal((B, 3, M - 1))
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    pos = np.zeros((B, 3, M))
+    pos[:, :, 1:] = np.cumsum(u, axis=2)
+    return pos
+
+
+def test_wlc_keeps_unit_bonds():
+    """The fixed-point cycle contracts by ~15x per pass at dt = 1e-3: eight
+    passes hold every bond at unit length to 1e-9 over 2000 steps."""
+    x = oracle.step_wlc(_unit_chains(20, 16, 1), 0.1, 1e-3, 2000, iters=8, seed=1)
+    assert np.abs(np.linalg.norm(np.diff(x, axis=2), axis=1) - 1).max() < 1e-9
+
+
+def test_wlc_dumbbell_rotational_diffusion():
+    """One rigid bond between two unit-friction beads: the orientation
+    diffuses with D_r = 2 T-bar, so <u(t).u(0)> = exp(-4 T-bar t)."""
+    B, T, dt = 3000, 0.5, 1e-3
+    x0 = _unit_chains(B, 2, 3)
+    u0 = x0[:, :, 1] - x0[:, :, 0]
+    x, step = x0, 0
+    for t in (0.2, 0.4, 0.6):
+        n = int(round(t / dt)) - step
+        x = oracle.step_wlc(x, T, dt, n, iters=6, seed=4, step0=step)
+        step += n
+        c = ((x[:, :, 1] - x[:, :, 0]) * u0).sum(axis=1)
+        assert c.mean() == pytest.approx(np.exp(-4 * T * t), abs=4 * c.std() / np.sqrt(B))
+
+
+def test_wlc_centre_of_mass_diffusion():
+    """Internal forces cancel: the centre of mass of M unit-friction beads
+    diffuses with D = T-bar / M."""
+    B, M, T, dt, n = 2000, 5, 0.3, 2e-3, 500
+    x0 = _unit_chains(B, M, 5)
+    x = oracle.step_wlc(x0, T, dt, n, iters=6, seed=6)
+    d2 = ((x.mean(axis=2) - x0.mean(axis=2)) ** 2).sum(axis=1)
+    want = 6 * T / M * n * dt
+    assert d2.mean() == pytest.approx(want, abs=4 * d2.std() / np.sqrt(B))
+
+
+def test_wlc_trimer_angle_follows_the_constrained_ensemble():
+    """Two rigid bonds: without metric pseudo-forces the constrained dynamics
+    samples exp(cos(theta)/T-bar) sqrt(det G), G the constraint metric
+    (det G ~ 4 - cos^2 theta for unit bonds and unit frictions), not the
+    stiff-spring law exp(cos(theta)/T-bar) alone; quadrature of both, the
+    sampled mean matches the first.  (At dsDNA stiffness, T-bar = 1/114,
+    the two differ by O(T-bar^2).)"""
+    T = 0.5
+    w = lambda c, k, g: c ** k * np.exp(c / T) * (np.sqrt(4 - c * c) if g else 1.0)
+    rigid = scipy.integrate.quad(w, -1, 1, args=(1, 1))[0] / scipy.integrate.quad(w, -1, 1, args=(0, 1))[0]
+    stiff = scipy.integrate.quad(w, -1, 1, args=(1, 0))[0] / scipy.integrate.quad(w, -1, 1, args=(0, 0))[0]
+    B, dt = 2000, 2e-3
+    x = oracle.step_wlc(_unit_chains(B, 3, 7), T, dt, 2000, iters=6, seed=8)
+    vals, step = [], 2000
+    for _ in range(15):
+        x = oracle.step_wlc(x, T, dt, 200, iters=6, seed=8, step0=step)
+        step += 200
+        u = np.diff(x, axis=2)
+        vals.append((u[:, :, 1] * u[:, :, 0]).sum(axis=1).mean())
+    v = np.array(vals)
+    se = v.std() / np.sqrt(v.size)
+    assert abs(v.mean() - rigid) < 4 * se, (v.mean(), rigid, se)
+    assert abs(stiff - rigid) > 4 * se
