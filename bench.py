@@ -27,7 +27,7 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--workload", default="modes",
-                    choices=["modes", "uneven", "shear", "mc", "dtmax", "dtmax_t"],
+                    choices=["modes", "uneven", "shear", "mc", "dtmax", "dtmax_t", "wlc"],
                     help="modes: 4096 x 256 bp (the headline line); uneven: 8192 chains of "
                          "64..512 bp in one launch; shear: 2048 x 256 bp under simple shear "
                          "at Wi = 1, 10, 100 (tumbling and extension, FP32 vs FP64); mc: "
@@ -390,10 +390,10 @@ def dtmax_t_workload(args):
                     qb, _ = decay(ref, i, t)
                     if qa is None or qb is None or qb == 0:
                         continue
-                    r = qa / qb
+                    r = float(qa / qb)
                     ratios[f"{name}@{tt:g}"] = r
                     ok = ok and abs(r - 1) <= 0.10
-            rows.append({"dtau": dt, "ratios": ratios, "within_10pct": ok})
+            rows.append({"dtau": dt, "ratios": ratios, "within_10pct": bool(ok)})
             print(f"# M={M} dtau={dt}: ok={ok} {ratios}", file=sys.stderr, flush=True)
         passed = []
         for r in rows:
@@ -409,8 +409,82 @@ def dtmax_t_workload(args):
                       "results": out}))
 
 
+def wlc_workload(args):
+    """Sec. 6a: the largest time step of the inextensible limit (Eqs. y2-y14)
+    for N = 63 at the persistence length of dsDNA (T-bar = a / l_p = 1/114.4).
+    From exact discrete-wormlike-chain starts: the time averages of <L^2> and
+    of the mean square distance of the middle bead from the centre of mass
+    must stay within 5 % of their closed forms, and the mean square
+    displacement of the middle bead (about the centre of mass) at times
+    0.002 * 2^k within 5 % of the smallest time step's.  The extensible model
+    under the bead Euler scheme is safe at dtau = 0.1 (Sec. 3a), i.e. at
+    dtau-bar = nu dtau = 0.035."""
+    import numpy as np
+    import torch
+    from paper_1411_3487_amd import Context, NU_DSDNA
+    from paper_1411_3487_amd.inputs import unit_chains
+    torch.cuda.set_device(0)
+    B, M, T = 8192, 64, 1.0 / 114.4
+    c = 1 / np.tanh(1 / T) - T                     # <u_n . u_(n+1)>, bond angles independent
+    f = lambda m: m + 2 * sum((m - k) * c ** k for k in range(1, m))   # <|r_i - r_(i+m)|^2>
+    mid = (M - 1) // 2
+    L2 = f(M - 1)
+    d2 = (sum(f(abs(mid - j)) for j in range(M)) / M
+          - sum(f(abs(j - k)) for j in range(M) for k in range(M)) / (2 * M * M))
+    pos0 = unit_chains(B, M, seed=11, T_bar=T)
+    times = [0.002 * 2 ** k for k in range(8)]
+
+    def rel_mid(x):
+        return x[:, :, mid] - x.mean(axis=2)
+    dm0 = rel_mid(pos0)
+    rows, ref = [], None
+    for dt in [1e-5, 2e-5, 5e-5, 1e-4, 2e-4, 5e-4, 1e-3, 2e-3, 4e-3, 8e-3]:
+        t0 = time.perf_counter()
+        l2, dm, msd, fin, done = [], [], {}, True, 0
+        with Context(pos0, seed=13, precision="fp64") as ctx:
+            for t in times:
+                n = int(round(t / dt)) - done
+                if n <= 0:
+                    continue
+                ctx.step_wlc(n, dt, T)
+                done += n
+                x = ctx.positions()
+                fin = fin and bool(np.all(np.isfinite(x)))
+                L = x[:, :, -1] - x[:, :, 0]
+                d = rel_mid(x)
+                l2.append((L * L).sum(axis=1).mean())
+                dm.append((d * d).sum(axis=1).mean())
+                msd[t] = float(((d - dm0) ** 2).sum(axis=1).mean())
+        if ref is None:
+            ref = msd
+        r = {"dtau_bar": dt, "steps": done, "L2_ratio": float(np.mean(l2) / L2),
+             "dmid2_ratio": float(np.mean(dm) / d2),
+             "msd_mid_ratio": {f"{t:g}": msd[t] / ref[t] for t in msd},
+             "finite": fin, "seconds": round(time.perf_counter() - t0, 2)}
+        r["within_5pct"] = bool(fin and abs(r["L2_ratio"] - 1) < 0.05
+                                and abs(r["dmid2_ratio"] - 1) < 0.05
+                                and all(abs(v - 1) < 0.05 for v in r["msd_mid_ratio"].values()))
+        rows.append(r)
+        print(f"# dt_bar={dt}: {r}", file=sys.stderr, flush=True)
+    ok = []
+    for r in rows:
+        if not r["within_5pct"]:
+            break
+        ok.append(r["dtau_bar"])
+    wlc_max = ok[-1] if ok else None
+    ext = 0.1 * NU_DSDNA
+    print(json.dumps({"workload": f"inextensible limit, {B} chains of {M} beads, T_bar = 1/114.4",
+                      "theory": {"L2": L2, "dmid2": d2, "bond_cos": c},
+                      "msd_mid_ref": {f"{t:g}": v for t, v in ref.items()},
+                      "runs": rows, "dtau_bar_max_wlc": wlc_max,
+                      "dtau_bar_max_extensible_euler": ext,
+                      "gain": (ext / wlc_max) if wlc_max else None}))
+
+
 def main():
     args = parse()
+    if args.workload == "wlc" and args.gpus == 1:
+        return wlc_workload(args)
     if args.workload == "dtmax_t" and args.gpus == 1:
         return dtmax_t_workload(args)
     if args.workload == "mc" and args.gpus == 1:

@@ -37,7 +37,8 @@
  *    (step hi << 8) | (component << 4) | tag); the four outputs give two
  *    Box-Muller pairs, normal j of the block belongs to index 4*(index/4)+j.
  *    tag 0 = mode step (index = mode p), 1 = Euler step (index = bead n),
- *    2 = Monte Carlo sweep (index = mode p, see dm_step_mc).
+ *    2 = Monte Carlo sweep (index = mode p, see dm_step_mc),
+ *    3 = inextensible limit (index = bead n, see dm_step_wlc).
  *    Results are therefore independent of how chains are batched.
  */
 #ifndef DNAMODES_H
@@ -210,6 +211,25 @@ int dm_step_modes(dm_ctx *ctx, int64_t n_steps);
    The scheme is unstable for dtau above about 0.3 (Sec. 3a).
    Errors: DM_ESTATE, DM_EINVAL (dtau <= 0), DM_ENONFINITE (check_finite). */
 int dm_step_euler(dm_ctx *ctx, int64_t n_steps, double dtau);
+
+/* The nu -> 0 limit (Sec. 5c, Eqs. y2-y14): the inextensible wormlike chain
+   in the bending units tau-bar = nu tau, T-bar = T* / nu, Hamiltonian
+   -sum_n u_n . u_{n+1} with bonds of unit length held by tensions f_n.  The
+   bonds of every chain are first scaled to unit length (positions then in
+   units of the bond length); each step moves bead n by
+   (-f_n u^m_n + f_{n+1} u^m_{n+1} + h_{n+1} - h_n) dt_bar
+   + sqrt(2 T_bar dt_bar) eta_n with the bending gradient
+   h_n = -(u^m_{n-1} + u^m_{n+1}) and the tensions from the tridiagonal
+   system (u_n + u'_n) . du_n = 0, all at the midpoint bonds
+   u^m_n = (u_n + u'_n)/|u_n + u'_n| (Eq. y14); the cycle is repeated iters
+   times from u' = u (8 holds the bonds at unit length to ~1e-12 per step at
+   dt_bar = 1e-3).  FP64, one thread per chain, noise tag 3 (index = bead).
+   The state is converted from and back to mode amplitudes once per call.
+   Without metric pseudo-forces the scheme samples the constrained ensemble
+   exp(-H/T_bar) sqrt(det G), G the constraint metric.  Errors: DM_EINVAL
+   (n_steps < 0, dt_bar or T_bar <= 0, iters outside 1..64), DM_ENONFINITE. */
+int dm_step_wlc(dm_ctx *ctx, int64_t n_steps, double dt_bar, double T_bar,
+                int32_t iters);
 
 /* Metropolis Monte Carlo in the mode representation, the paper's benchmark
    for equilibrium values (Sec. 6: large steps in the slow modes, small in

@@ -47,6 +47,7 @@ struct Bucket {
     double *d_chiT = nullptr;        // chi_{n,p} at [p][n-1], M x (M-1)
     double *d_mcstep = nullptr;      // proposal half-widths s_p
     int64_t *d_mcacc = nullptr;      // accepted proposals per chain
+    double *d_wlc = nullptr;         // scratch of the inextensible limit
     std::vector<double> zeta_l;      // host zeta^l_p of the current parameters
     std::vector<double> mcstep_h;    // host copy of s_p (kept alive for the upload)
     double *d_cm0 = nullptr;         // n*3
@@ -124,7 +125,7 @@ void free_bucket(Bucket &b)
     void *ptrs[] = {b.d_ids, b.d_off,  b.d_Ainv, b.d_Apos, b.d_Afwd, b.d_E,   b.d_C,
                     b.d_W,   b.d_R64, b.d_r,    b.d_F,    b.d_dH,   b.d_obs, b.d_m2,
                     b.d_acc, b.d_accsum, b.d_cm0, b.d_tumble, b.d_chiT, b.d_mcstep,
-                    b.d_mcacc, b.d_ring, b.d_ccount};
+                    b.d_mcacc, b.d_ring, b.d_ccount, b.d_wlc};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     dm::fused_free(b.fused);
@@ -546,6 +547,32 @@ int dm_step_euler(dm_ctx *ctx, int64_t n_steps, double dtau)
         if (rc) return rc;
         DM_HIP(ctx, dm::launch_euler_f64(b.d_r, b.d_ids, b.M, b.n, ctx->nu, dtau, ctx->T_star,
                                          gdt, ctx->seed, ctx->step, (int)n_steps, ctx->stream));
+        DM_HIP(ctx, dm::launch_gemm_f64(b.d_Afwd, b.d_r, b.d_R64, b.M, 3 * b.n, ctx->stream));
+        if (fused_precision(ctx->precision))
+            DM_HIP(ctx, dm::fused_pack_modes(b.fused, b.d_R64, b.M, b.n, ctx->stream));
+    }
+    ctx->step += n_steps;
+    if (ctx->check_finite) return check_state(ctx);
+    return DM_OK;
+}
+
+int dm_step_wlc(dm_ctx *ctx, int64_t n_steps, double dt_bar, double T_bar, int32_t iters)
+{
+    if (!ctx) return DM_EINVAL;
+    if (n_steps < 0 || n_steps > (1 << 30)) return fail(ctx, DM_EINVAL, "bad n_steps");
+    if (!(dt_bar > 0.0) || !std::isfinite(dt_bar) || !(T_bar > 0.0) || !std::isfinite(T_bar))
+        return fail(ctx, DM_EINVAL, "dt_bar and T_bar must be positive");
+    if (iters < 1 || iters > 64) return fail(ctx, DM_EINVAL, "iters must be 1..64");
+    if (n_steps == 0) return DM_OK;
+    for (Bucket &b : ctx->buckets) {
+        if (!b.d_wlc) {
+            int rc = dalloc(ctx, &b.d_wlc, dm::wlc_scratch_doubles(b.M, b.n));
+            if (rc) return rc;
+        }
+        int rc = bucket_positions(ctx, b, ctx->stream);  // b.d_r = phi R (FP64)
+        if (rc) return rc;
+        DM_HIP(ctx, dm::launch_wlc(b.d_r, b.d_wlc, b.d_ids, b.M, b.n, T_bar, dt_bar, iters,
+                                   ctx->seed, ctx->step, (int)n_steps, ctx->stream));
         DM_HIP(ctx, dm::launch_gemm_f64(b.d_Afwd, b.d_r, b.d_R64, b.M, 3 * b.n, ctx->stream));
         if (fused_precision(ctx->precision))
             DM_HIP(ctx, dm::fused_pack_modes(b.fused, b.d_R64, b.M, b.n, ctx->stream));

@@ -66,6 +66,14 @@ hipError_t launch_euler_f64(double *pos, const int32_t *ids, int M, int nch,
                             uint64_t seed, int64_t step0, int n_steps,
                             hipStream_t st);
 
+// n_steps of the inextensible limit (Eqs. y2-y14) on positions pos (SoA,
+// nch chains of M beads with unit bonds), one thread per chain; scr holds
+// wlc_scratch_doubles(M, nch) doubles.
+size_t wlc_scratch_doubles(int M, int nch);
+hipError_t launch_wlc(double *pos, double *scr, const int32_t *ids, int M, int nch, double T_bar,
+                      double dt, int iters, uint64_t seed, int64_t step0, int n_steps,
+                      hipStream_t st);
+
 // n_sweeps Metropolis sweeps of the FP64 amplitudes R (nch chains of 3*M),
 // with chiT[p*(M-1) + n-1] = chi_{n,p} and step half-widths sstep[p]; the
 // accepted proposals of chain c go to accepted[c].

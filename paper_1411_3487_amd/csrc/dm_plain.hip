@@ -433,6 +433,123 @@ __global__ __launch_bounds__(64) void mc_kernel(double *__restrict__ R,
     if (lane == 0) accepted[c] = acc;
 }
 
+// The nu -> 0 limit (Sec. 5c, Eqs. y2-y14), one thread per chain, FP64: the
+// inextensible chain in bending units (tau-bar, T-bar), bonds of unit
+// length held by tensions.  A step moves bead n by
+//   dr_n = (-f_n u^m_n + f_{n+1} u^m_{n+1} + h_{n+1} - h_n) dt + sqrt(2 T-bar dt) eta_n,
+// h_n = -(u^m_{n-1} + u^m_{n+1}) the bending gradient, u^m_n = (u_n + u'_n) /
+// |u_n + u'_n| the midpoint bonds (Eq. y14); the tensions f_n solve the
+// tridiagonal system (u_n + u'_n) . du_n = 0 (Eqs. y11-y13) by the Thomas
+// algorithm, and the cycle (midpoint, tensions, u') is repeated `iters`
+// times from u' = u.  Scratch, chain-fastest ([index][chain], coalesced):
+// u, u', u^m (3 (N+2) each, bonds 0 and N+1 zero), noise (3 (N+1)), the
+// Thomas coefficients c', d' (N each) and f (N+2).  Noise: the bead index
+// with tag 3.  The bonds are scaled to unit length on entry.
+__global__ __launch_bounds__(64) void wlc_kernel(double *__restrict__ pos,
+                                                 double *__restrict__ scr,
+                                                 const int32_t *__restrict__ ids, int M, int nch,
+                                                 double T_bar, double dt, int iters,
+                                                 uint64_t seed, int64_t step0, int n_steps)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nch) return;
+    const int N = M - 1;
+    const size_t S = (size_t)nch;
+    double *U = scr, *UN = U + 3 * (size_t)(N + 2) * S, *UM = UN + 3 * (size_t)(N + 2) * S;
+    double *NZ = UM + 3 * (size_t)(N + 2) * S, *CP = NZ + 3 * (size_t)(N + 1) * S;
+    double *DP = CP + (size_t)N * S, *F = DP + (size_t)N * S;
+#define V3(A, n, a) A[((size_t)3 * (n) + (a)) * S + c]
+    double *x = pos + (size_t)c * 3 * M;
+    const uint32_t chain = (uint32_t)ids[c];
+    const double amp = sqrt(2.0 * T_bar * dt);
+    for (int a = 0; a < 3; ++a) {
+        V3(U, 0, a) = V3(U, N + 1, a) = 0.0;
+        V3(UN, 0, a) = V3(UN, N + 1, a) = 0.0;
+        V3(UM, 0, a) = V3(UM, N + 1, a) = 0.0;
+    }
+    for (int n = 1; n <= N; ++n) {  // bonds, scaled to unit length
+        double u[3], s2 = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            u[a] = x[a * M + n] - x[a * M + n - 1];
+            s2 += u[a] * u[a];
+        }
+        const double inv = s2 > 0.0 ? 1.0 / sqrt(s2) : 0.0;
+        for (int a = 0; a < 3; ++a) V3(U, n, a) = u[a] * inv;
+    }
+    F[0 * S + c] = 0.0;
+    F[(size_t)(N + 1) * S + c] = 0.0;
+    double r0[3] = {x[0], x[M], x[2 * M]};
+    // regular displacement of bead n (bending at the midpoint bonds + noise)
+    auto drr = [&](int n, int a) {
+        const double hn = n >= 1 ? -(V3(UM, n - 1, a) + V3(UM, n + 1, a)) : 0.0;
+        const double hn1 = n + 1 <= N ? -(V3(UM, n, a) + V3(UM, n + 2 <= N + 1 ? n + 2 : N + 1, a))
+                                      : 0.0;
+        return (hn1 - hn) * dt + V3(NZ, n, a);
+    };
+    for (int s = 0; s < n_steps; ++s) {
+        const int64_t k = step0 + s;
+        for (int a = 0; a < 3; ++a)
+            for (int q = 0; q <= N / 4; ++q) {
+                double z[4];
+                normals4_f64(noise_bits(seed, (uint32_t)q, chain, k, (uint32_t)a, kTagWLC), z);
+                for (int e = 0; e < 4 && 4 * q + e <= N; ++e) V3(NZ, 4 * q + e, a) = amp * z[e];
+            }
+        for (int n = 1; n <= N; ++n)
+            for (int a = 0; a < 3; ++a) V3(UN, n, a) = V3(U, n, a);
+        for (int it = 0; it < iters; ++it) {
+            for (int n = 1; n <= N; ++n) {
+                double w[3], s2 = 0.0;
+                for (int a = 0; a < 3; ++a) {
+                    w[a] = V3(U, n, a) + V3(UN, n, a);
+                    s2 += w[a] * w[a];
+                }
+                const double inv = 1.0 / sqrt(s2);
+                for (int a = 0; a < 3; ++a) V3(UM, n, a) = w[a] * inv;
+            }
+            // Thomas forward sweep: a f_{n-1} + b f_n + c f_{n+1} = r
+            double cp = 0.0, dp = 0.0;
+            for (int n = 1; n <= N; ++n) {
+                double wl = 0.0, wm = 0.0, wr = 0.0, wd = 0.0;
+                for (int a = 0; a < 3; ++a) {
+                    const double w = V3(U, n, a) + V3(UN, n, a);
+                    wl += w * V3(UM, n - 1, a);
+                    wm += w * V3(UM, n, a);
+                    wr += w * V3(UM, n + 1, a);
+                    wd += w * (drr(n, a) - drr(n - 1, a));
+                }
+                const double ca = wl * dt, cb = -2.0 * wm * dt, cc = wr * dt, rr = -wd;
+                const double m = n == 1 ? cb : cb - ca * cp;
+                cp = cc / m;
+                dp = (n == 1 ? rr : rr - ca * dp) / m;
+                CP[(size_t)(n - 1) * S + c] = cp;
+                DP[(size_t)(n - 1) * S + c] = dp;
+            }
+            double fn = DP[(size_t)(N - 1) * S + c];
+            F[(size_t)N * S + c] = fn;
+            for (int n = N - 1; n >= 1; --n) {
+                fn = DP[(size_t)(n - 1) * S + c] - CP[(size_t)(n - 1) * S + c] * fn;
+                F[(size_t)n * S + c] = fn;
+            }
+            for (int n = 1; n <= N; ++n) {
+                const double fl = F[(size_t)(n - 1) * S + c], fm = F[(size_t)n * S + c],
+                             fr = F[(size_t)(n + 1) * S + c];
+                for (int a = 0; a < 3; ++a)
+                    V3(UN, n, a) = V3(U, n, a) + (drr(n, a) - drr(n - 1, a)) +
+                                   (fl * V3(UM, n - 1, a) - 2.0 * fm * V3(UM, n, a) +
+                                    fr * V3(UM, n + 1, a)) * dt;
+            }
+        }
+        for (int a = 0; a < 3; ++a) r0[a] += drr(0, a) + F[(size_t)1 * S + c] * V3(UM, 1, a) * dt;
+        for (int n = 1; n <= N; ++n)
+            for (int a = 0; a < 3; ++a) V3(U, n, a) = V3(UN, n, a);
+    }
+    for (int a = 0; a < 3; ++a) {
+        x[a * M] = r0[a];
+        for (int n = 1; n <= N; ++n) x[a * M + n] = x[a * M + n - 1] + V3(U, n, a);
+    }
+#undef V3
+}
+
 __global__ void reduce_chains_kernel(const double *__restrict__ acc, double *__restrict__ out,
                                      int width, int nch)
 {
@@ -509,6 +626,23 @@ hipError_t launch_euler_f64(double *pos, const int32_t *ids, int M, int nch, dou
     if (lds > 64 * 1024) return hipErrorInvalidValue;  // positions must fit the LDS
     hipLaunchKernelGGL(euler_f64_kernel, dim3(nch), dim3(threads), lds, st, pos, ids, M, nu,
                        dtau, sqrt(2.0 * T_star * dtau), gdt, seed, step0, n_steps);
+    return hipGetLastError();
+}
+
+size_t wlc_scratch_doubles(int M, int nch)
+{
+    const size_t N = (size_t)M - 1;
+    return (9 * (N + 2) + 3 * (N + 1) + 2 * N + (N + 2)) * (size_t)nch;
+}
+
+hipError_t launch_wlc(double *pos, double *scr, const int32_t *ids, int M, int nch, double T_bar,
+                      double dt, int iters, uint64_t seed, int64_t step0, int n_steps,
+                      hipStream_t st)
+{
+    if (nch == 0 || n_steps == 0) return hipSuccess;
+    if (M < 2 || iters < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(wlc_kernel, dim3((nch + 63) / 64), dim3(64), 0, st, pos, scr, ids, M, nch,
+                       T_bar, dt, iters, seed, step0, n_steps);
     return hipGetLastError();
 }
 

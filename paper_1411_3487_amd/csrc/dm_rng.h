@@ -15,7 +15,7 @@
 
 namespace dm {
 
-enum : uint32_t { kTagMode = 0u, kTagEuler = 1u, kTagMC = 2u };
+enum : uint32_t { kTagMode = 0u, kTagEuler = 1u, kTagMC = 2u, kTagWLC = 3u };
 
 struct Block4 {
     uint32_t v[4];

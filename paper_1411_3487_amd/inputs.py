@@ -57,3 +57,37 @@ def mixed_chains(beads: np.ndarray, spacing: float, seed: int,
         p = e[:, None] * n[None, :] + jitter * spacing * rng.standard_normal((3, int(M)))
         out.append(p)
     return out
+
+
+def unit_chains(n_chains: int, M: int, seed: int, T_bar: float | None = None) -> np.ndarray:
+    """Chains of M beads joined by unit bonds, (n_chains, 3, M), first bead at
+    the origin.  With T_bar None the bond directions are independent and
+    uniform; otherwise the chain is a discrete wormlike chain in equilibrium
+    at reduced temperature T_bar: each bond angle to the previous bond is
+    independent with density ~ exp(cos(theta) / T_bar), sampled by inverting
+    its distribution in cos(theta), and the azimuth is uniform."""
+    if M < 2:
+        return np.zeros((n_chains, 3, M))
+    rng = np.random.default_rng(seed)
+    u = np.zeros((n_chains, 3, M - 1))
+    v = rng.standard_normal((n_chains, 3))
+    u[:, :, 0] = v / np.linalg.norm(v, axis=1, keepdims=True)
+    for n in range(1, M - 1):
+        if T_bar is None:
+            v = rng.standard_normal((n_chains, 3))
+            u[:, :, n] = v / np.linalg.norm(v, axis=1, keepdims=True)
+            continue
+        x = rng.random(n_chains)
+        ct = 1 + T_bar * np.log(x + (1 - x) * np.exp(-2 / T_bar))
+        ph = 2 * np.pi * rng.random(n_chains)
+        p = u[:, :, n - 1]
+        a = np.where(np.abs(p[:, :1]) < 0.9, np.array([[1.0, 0, 0]]), np.array([[0, 1.0, 0]]))
+        e1 = np.cross(p, a)
+        e1 /= np.linalg.norm(e1, axis=1, keepdims=True)
+        e2 = np.cross(p, e1)
+        st = np.sqrt(np.maximum(0, 1 - ct ** 2))
+        u[:, :, n] = ct[:, None] * p + st[:, None] * (np.cos(ph)[:, None] * e1 +
+                                                      np.sin(ph)[:, None] * e2)
+    pos = np.zeros((n_chains, 3, M))
+    pos[:, :, 1:] = np.cumsum(u, axis=2)
+    return pos
