@@ -409,6 +409,13 @@ def dtmax_t_workload(args):
                       "results": out}))
 
 
+# Floating-point operations of one tension cycle per bond of the inextensible
+# stepper (Eqs. y9-y14), counted as written with a Thomas solve: midpoint
+# bond 13 (sqrt and divide counted as one), bending displacements 12, the
+# tridiagonal row 27, its solve 8, the bond update 25.
+WLC_FLOPS_PER_BOND_ITER = 85
+
+
 def wlc_workload(args):
     """Sec. 6a: the largest time step of the inextensible limit (Eqs. y2-y14)
     for N = 63 at the persistence length of dsDNA (T-bar = a / l_p = 1/114.4).
@@ -416,7 +423,7 @@ def wlc_workload(args):
     of the mean square distance of the middle bead from the centre of mass
     must stay within 5 % of their closed forms, and the mean square
     displacement of the middle bead (about the centre of mass) at times
-    0.002 * 2^k within 5 % of the smallest time step's.  The extensible model
+    0.002 * 2^k up to 1.024 within 5 % of the smallest time step's.  The extensible model
     under the bead Euler scheme is safe at dtau = 0.1 (Sec. 3a), i.e. at
     dtau-bar = nu dtau = 0.035."""
     import numpy as np
@@ -432,35 +439,40 @@ def wlc_workload(args):
     d2 = (sum(f(abs(mid - j)) for j in range(M)) / M
           - sum(f(abs(j - k)) for j in range(M) for k in range(M)) / (2 * M * M))
     pos0 = unit_chains(B, M, seed=11, T_bar=T)
-    times = [0.002 * 2 ** k for k in range(8)]
+    times = [0.002 * 2 ** k for k in range(10)]
 
     def rel_mid(x):
         return x[:, :, mid] - x.mean(axis=2)
     dm0 = rel_mid(pos0)
     rows, ref = [], None
-    for dt in [1e-5, 2e-5, 5e-5, 1e-4, 2e-4, 5e-4, 1e-3, 2e-3, 4e-3, 8e-3]:
+    for dt in [2e-5, 5e-5, 1e-4, 2e-4, 5e-4, 1e-3, 2e-3, 4e-3, 8e-3, 1.6e-2, 3.2e-2, 6.4e-2]:
         t0 = time.perf_counter()
-        l2, dm, msd, fin, done = [], [], {}, True, 0
+        l2, dm, bend, msd, fin, done = [], [], [], {}, True, 0
         with Context(pos0, seed=13, precision="fp64") as ctx:
             for t in times:
                 n = int(round(t / dt)) - done
                 if n <= 0:
                     continue
-                ctx.step_wlc(n, dt, T)
+                ctx.step_wlc(n, dt, T, iters=16, tol=1e-12)
                 done += n
                 x = ctx.positions()
                 fin = fin and bool(np.all(np.isfinite(x)))
                 L = x[:, :, -1] - x[:, :, 0]
                 d = rel_mid(x)
+                u = np.diff(x, axis=2)
+                bend.append(1 - (u[:, :, 1:] * u[:, :, :-1]).sum(axis=1).mean())
                 l2.append((L * L).sum(axis=1).mean())
                 dm.append((d * d).sum(axis=1).mean())
                 msd[t] = float(((d - dm0) ** 2).sum(axis=1).mean())
+            bond_err = float(np.abs(np.linalg.norm(np.diff(x, axis=2), axis=1) - 1).max())
         if ref is None:
             ref = msd
         r = {"dtau_bar": dt, "steps": done, "L2_ratio": float(np.mean(l2) / L2),
              "dmid2_ratio": float(np.mean(dm) / d2),
+             "bend_ratio": float(np.mean(bend) / (1 - c)),
              "msd_mid_ratio": {f"{t:g}": msd[t] / ref[t] for t in msd},
-             "finite": fin, "seconds": round(time.perf_counter() - t0, 2)}
+             "bond_err": bond_err, "finite": fin,
+             "seconds": round(time.perf_counter() - t0, 2)}
         r["within_5pct"] = bool(fin and abs(r["L2_ratio"] - 1) < 0.05
                                 and abs(r["dmid2_ratio"] - 1) < 0.05
                                 and all(abs(v - 1) < 0.05 for v in r["msd_mid_ratio"].values()))
@@ -473,10 +485,45 @@ def wlc_workload(args):
         ok.append(r["dtau_bar"])
     wlc_max = ok[-1] if ok else None
     ext = 0.1 * NU_DSDNA
+    # throughput of the stepper: HIP events around one call on the context's stream
+    stream = torch.cuda.current_stream()
+    n_t, iters = 2000, 8
+    with Context(pos0, seed=13, precision="fp64", stream=stream) as ctx:
+        ctx.step_wlc(10, 1e-4, T, iters=iters)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        ctx.step_wlc(n_t, 1e-4, T, iters=iters)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        sec = e0.elapsed_time(e1) * 1e-3
+        e0.record(stream)
+        ctx.step_wlc(n_t, 1e-4, T, iters=16, tol=1e-12)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        sec_conv = e0.elapsed_time(e1) * 1e-3
+    flops = WLC_FLOPS_PER_BOND_ITER * iters * (M - 1)      # per chain-step
+    peak = 78.6e12
+    perf = {"chain_steps_per_s": B * n_t / sec, "us_per_step": sec / n_t * 1e6,
+            "iters": iters, "us_per_step_converged_1e-12": sec_conv / n_t * 1e6,
+            "roofline": {"bound": "alu", "achieved": flops * B * n_t / sec / 1e12,
+                         "peak": peak / 1e12, "unit": "TFLOP/s",
+                         "frac": flops * B * n_t / sec / peak,
+                         "flops_per_chain_step": flops}}
+    if not args.no_cpu_baseline:
+        import oracle
+        sample = pos0[:16]
+        t0 = time.perf_counter()
+        oracle.step_wlc(sample, T, 1e-4, 200, iters=iters, seed=13)
+        cs = time.perf_counter() - t0
+        perf["cpu_baseline"] = {"value": 16 * 200 / cs, "unit": "chain-steps/s", "cores": 1,
+                                "kind": "oracle",
+                                "sample": "16 of the chains, 200 steps at dtau-bar = 1e-4"}
+    print(f"# stepper: {perf}", file=sys.stderr, flush=True)
     print(json.dumps({"workload": f"inextensible limit, {B} chains of {M} beads, T_bar = 1/114.4",
                       "theory": {"L2": L2, "dmid2": d2, "bond_cos": c},
                       "msd_mid_ref": {f"{t:g}": v for t, v in ref.items()},
-                      "runs": rows, "dtau_bar_max_wlc": wlc_max,
+                      "runs": rows, "stepper": perf, "dtau_bar_max_wlc": wlc_max,
                       "dtau_bar_max_extensible_euler": ext,
                       "gain": (ext / wlc_max) if wlc_max else None}))
 

@@ -221,15 +221,21 @@ int dm_step_euler(dm_ctx *ctx, int64_t n_steps, double dtau);
    + sqrt(2 T_bar dt_bar) eta_n with the bending gradient
    h_n = -(u^m_{n-1} + u^m_{n+1}) and the tensions from the tridiagonal
    system (u_n + u'_n) . du_n = 0, all at the midpoint bonds
-   u^m_n = (u_n + u'_n)/|u_n + u'_n| (Eq. y14); the cycle is repeated iters
-   times from u' = u (8 holds the bonds at unit length to ~1e-12 per step at
-   dt_bar = 1e-3).  FP64, one thread per chain, noise tag 3 (index = bead).
+   u^m_n = (u_n + u'_n)/|u_n + u'_n| (Eq. y14).  The cycle starts from
+   u' = u and is repeated until it converges: at most iters times, and with
+   tol > 0 it stops after the first cycle that changes no component of any
+   u'_n by more than tol (tol = 0: exactly iters cycles; 8 cycles hold the
+   bonds at unit length to ~1e-12 per step at dt_bar = 1e-3).  FP64: one
+   wavefront per chain with the chain in LDS up to M = 341 (tensions by
+   cyclic reduction), one thread per chain beyond (Thomas sweep, global
+   scratch allocated on first use); noise tag 3 (index = bead).
    The state is converted from and back to mode amplitudes once per call.
    Without metric pseudo-forces the scheme samples the constrained ensemble
    exp(-H/T_bar) sqrt(det G), G the constraint metric.  Errors: DM_EINVAL
-   (n_steps < 0, dt_bar or T_bar <= 0, iters outside 1..64), DM_ENONFINITE. */
+   (n_steps < 0, dt_bar or T_bar <= 0, iters outside 1..64, tol < 0 or not
+   finite), DM_ENONFINITE. */
 int dm_step_wlc(dm_ctx *ctx, int64_t n_steps, double dt_bar, double T_bar,
-                int32_t iters);
+                int32_t iters, double tol);
 
 /* Metropolis Monte Carlo in the mode representation, the paper's benchmark
    for equilibrium values (Sec. 6: large steps in the slow modes, small in

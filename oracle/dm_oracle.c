@@ -391,7 +391,9 @@ double orc_energy(int M, double nu, const double *pos)
 /*   (u_n + u'_n) . du_n = 0,                                                */
 /*   du_n = (f_{n-1} u^m_{n-1} - 2 f_n u^m_n + f_{n+1} u^m_{n+1}) dt + D_n,   */
 /* D_n the regular part of dr_n - dr_{n-1}.  Starting from u' = u the cycle  */
-/* (midpoint, forces, tensions, u') is repeated `iters` times.  Bonds are    */
+/* (midpoint, forces, tensions, u') is repeated until it converges: at most */
+/* `iters` times, and with tol > 0 it stops after the first cycle that     */
+/* changes no component of any u'_n by more than tol.  Bonds are            */
 /* numbered n = 1..N (N = M - 1); f, h, u vanish outside.  Noise: the Euler  */
 /* convention with tag 3.  pos is 3*M per chain; only the bonds and bead 0   */
 /* are advanced, and the positions rebuilt from them.                       */
@@ -412,7 +414,7 @@ static void wlc_solve(int N, const double *a, const double *b, const double *c,
 }
 
 void orc_step_wlc(int M, int n_chains, const uint32_t *chain_id, double *pos,
-                  double T_bar, double dt, int iters, uint64_t seed,
+                  double T_bar, double dt, int iters, double tol, uint64_t seed,
                   int64_t step0, int64_t n_steps)
 {
     const int N = M - 1;
@@ -487,12 +489,17 @@ void orc_step_wlc(int M, int n_chains, const uint32_t *chain_id, double *pos,
                     wlc_solve(N, A, Bd, Cd, Rr, X, cp, dp);
                     f[0] = f[N + 1] = 0.0;
                     for (int n = 1; n <= N; ++n) f[n] = X[n - 1];
+                    double change = 0.0;
                     for (int n = 1; n <= N; ++n)
-                        for (int a = 0; a < 3; ++a)
-                            un[3 * n + a] = u[3 * n + a] + D[3 * n + a] +
-                                            (f[n - 1] * um[3 * (n - 1) + a] -
-                                             2.0 * f[n] * um[3 * n + a] +
-                                             f[n + 1] * um[3 * (n + 1) + a]) * dt;
+                        for (int a = 0; a < 3; ++a) {
+                            const double v = u[3 * n + a] + D[3 * n + a] +
+                                             (f[n - 1] * um[3 * (n - 1) + a] -
+                                              2.0 * f[n] * um[3 * n + a] +
+                                              f[n + 1] * um[3 * (n + 1) + a]) * dt;
+                            change = fmax(change, fabs(v - un[3 * n + a]));
+                            un[3 * n + a] = v;
+                        }
+                    if (tol > 0.0 && change <= tol) break;
                 }
                 /* bead 0 moves with its own tension, bending and noise */
                 for (int a = 0; a < 3; ++a)

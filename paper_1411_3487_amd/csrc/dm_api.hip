@@ -556,22 +556,26 @@ int dm_step_euler(dm_ctx *ctx, int64_t n_steps, double dtau)
     return DM_OK;
 }
 
-int dm_step_wlc(dm_ctx *ctx, int64_t n_steps, double dt_bar, double T_bar, int32_t iters)
+int dm_step_wlc(dm_ctx *ctx, int64_t n_steps, double dt_bar, double T_bar, int32_t iters,
+                double tol)
 {
     if (!ctx) return DM_EINVAL;
     if (n_steps < 0 || n_steps > (1 << 30)) return fail(ctx, DM_EINVAL, "bad n_steps");
     if (!(dt_bar > 0.0) || !std::isfinite(dt_bar) || !(T_bar > 0.0) || !std::isfinite(T_bar))
         return fail(ctx, DM_EINVAL, "dt_bar and T_bar must be positive");
     if (iters < 1 || iters > 64) return fail(ctx, DM_EINVAL, "iters must be 1..64");
+    if (!(tol >= 0.0) || !std::isfinite(tol))
+        return fail(ctx, DM_EINVAL, "tol must be finite and >= 0");
     if (n_steps == 0) return DM_OK;
     for (Bucket &b : ctx->buckets) {
-        if (!b.d_wlc) {
-            int rc = dalloc(ctx, &b.d_wlc, dm::wlc_scratch_doubles(b.M, b.n));
+        const size_t scratch = dm::wlc_scratch_doubles(b.M, b.n);
+        if (scratch && !b.d_wlc) {
+            int rc = dalloc(ctx, &b.d_wlc, scratch);
             if (rc) return rc;
         }
         int rc = bucket_positions(ctx, b, ctx->stream);  // b.d_r = phi R (FP64)
         if (rc) return rc;
-        DM_HIP(ctx, dm::launch_wlc(b.d_r, b.d_wlc, b.d_ids, b.M, b.n, T_bar, dt_bar, iters,
+        DM_HIP(ctx, dm::launch_wlc(b.d_r, b.d_wlc, b.d_ids, b.M, b.n, T_bar, dt_bar, iters, tol,
                                    ctx->seed, ctx->step, (int)n_steps, ctx->stream));
         DM_HIP(ctx, dm::launch_gemm_f64(b.d_Afwd, b.d_r, b.d_R64, b.M, 3 * b.n, ctx->stream));
         if (fused_precision(ctx->precision))

@@ -440,15 +440,16 @@ __global__ __launch_bounds__(64) void mc_kernel(double *__restrict__ R,
 // h_n = -(u^m_{n-1} + u^m_{n+1}) the bending gradient, u^m_n = (u_n + u'_n) /
 // |u_n + u'_n| the midpoint bonds (Eq. y14); the tensions f_n solve the
 // tridiagonal system (u_n + u'_n) . du_n = 0 (Eqs. y11-y13) by the Thomas
-// algorithm, and the cycle (midpoint, tensions, u') is repeated `iters`
-// times from u' = u.  Scratch, chain-fastest ([index][chain], coalesced):
+// algorithm, and the cycle (midpoint, tensions, u') is repeated from u' = u
+// until it converges: at most `iters` times, fewer when tol > 0 and a cycle
+// moves no component of u' by more than tol.  Scratch, chain-fastest ([index][chain], coalesced):
 // u, u', u^m (3 (N+2) each, bonds 0 and N+1 zero), noise (3 (N+1)), the
 // Thomas coefficients c', d' (N each) and f (N+2).  Noise: the bead index
 // with tag 3.  The bonds are scaled to unit length on entry.
 __global__ __launch_bounds__(64) void wlc_kernel(double *__restrict__ pos,
                                                  double *__restrict__ scr,
                                                  const int32_t *__restrict__ ids, int M, int nch,
-                                                 double T_bar, double dt, int iters,
+                                                 double T_bar, double dt, int iters, double tol,
                                                  uint64_t seed, int64_t step0, int n_steps)
 {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
@@ -530,14 +531,19 @@ __global__ __launch_bounds__(64) void wlc_kernel(double *__restrict__ pos,
                 fn = DP[(size_t)(n - 1) * S + c] - CP[(size_t)(n - 1) * S + c] * fn;
                 F[(size_t)n * S + c] = fn;
             }
+            double change = 0.0;
             for (int n = 1; n <= N; ++n) {
                 const double fl = F[(size_t)(n - 1) * S + c], fm = F[(size_t)n * S + c],
                              fr = F[(size_t)(n + 1) * S + c];
-                for (int a = 0; a < 3; ++a)
-                    V3(UN, n, a) = V3(U, n, a) + (drr(n, a) - drr(n - 1, a)) +
-                                   (fl * V3(UM, n - 1, a) - 2.0 * fm * V3(UM, n, a) +
-                                    fr * V3(UM, n + 1, a)) * dt;
+                for (int a = 0; a < 3; ++a) {
+                    const double v = V3(U, n, a) + (drr(n, a) - drr(n - 1, a)) +
+                                     (fl * V3(UM, n - 1, a) - 2.0 * fm * V3(UM, n, a) +
+                                      fr * V3(UM, n + 1, a)) * dt;
+                    change = fmax(change, fabs(v - V3(UN, n, a)));
+                    V3(UN, n, a) = v;
+                }
             }
+            if (tol > 0.0 && change <= tol) break;
         }
         for (int a = 0; a < 3; ++a) r0[a] += drr(0, a) + F[(size_t)1 * S + c] * V3(UM, 1, a) * dt;
         for (int n = 1; n <= N; ++n)
@@ -548,6 +554,159 @@ __global__ __launch_bounds__(64) void wlc_kernel(double *__restrict__ pos,
         for (int n = 1; n <= N; ++n) x[a * M + n] = x[a * M + n - 1] + V3(U, n, a);
     }
 #undef V3
+}
+
+// The same step with one wavefront per chain and the chain in LDS: bonds and
+// beads are spread over the lanes, and the tension system is solved by
+// parallel cyclic reduction (each of ceil(log2 N) rounds eliminates the
+// couplings to the rows s apart, s = 1, 2, 4, ...) instead of the serial
+// Thomas sweep.  LDS, doubles ([axis][index]): u, u', u^m (3 (N+2) each),
+// noise and the regular displacements (3 (N+1) each), two sets of the
+// tridiagonal rows a, b, c, r (4 N each) and f (N+2): wlc_lds_doubles(M).
+constexpr size_t kWlcMaxLds = 64 * 1024;  // the wave kernel's LDS limit
+
+__host__ __device__ inline size_t wlc_lds_doubles(int M)
+{
+    const size_t N = (size_t)M - 1;
+    return 9 * (N + 2) + 6 * (N + 1) + 8 * N + (N + 2);
+}
+
+__global__ __launch_bounds__(64) void wlc_wave_kernel(double *__restrict__ pos,
+                                                      const int32_t *__restrict__ ids, int M,
+                                                      double T_bar, double dt, int iters,
+                                                      double tol, uint64_t seed, int64_t step0,
+                                                      int n_steps)
+{
+    extern __shared__ double lds[];
+    const int c = blockIdx.x, t = threadIdx.x;
+    const int N = M - 1, P = N + 2, Q = N + 1;
+    double *U = lds, *UN = U + 3 * P, *UM = UN + 3 * P;
+    double *NZ = UM + 3 * P, *D = NZ + 3 * Q;
+    double *const rows = D + 3 * Q;  // set h: a, b, c, r at rows + (4 h + 0..3) N
+    double *F = rows + 8 * (size_t)N;
+    double *x = pos + (size_t)c * 3 * M;
+    const uint32_t chain = (uint32_t)ids[c];
+    const double amp = sqrt(2.0 * T_bar * dt);
+    for (int i = t; i < 3 * P; i += 64) U[i] = UN[i] = UM[i] = 0.0;
+    for (int i = t; i < P; i += 64) F[i] = 0.0;
+    __syncthreads();
+    for (int n = 1 + t; n <= N; n += 64) {  // bonds, scaled to unit length
+        double u[3], s2 = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            u[a] = x[a * M + n] - x[a * M + n - 1];
+            s2 += u[a] * u[a];
+        }
+        const double inv = s2 > 0.0 ? 1.0 / sqrt(s2) : 0.0;
+        for (int a = 0; a < 3; ++a) U[a * P + n] = u[a] * inv;
+    }
+    double r0 = t < 3 ? x[t * M] : 0.0;
+    const int nq = N / 4 + 1;
+    __syncthreads();
+    for (int s = 0; s < n_steps; ++s) {
+        const int64_t k = step0 + s;
+        for (int i = t; i < 3 * nq; i += 64) {
+            const int a = i / nq, q = i - a * nq;
+            double z[4];
+            normals4_f64(noise_bits(seed, (uint32_t)q, chain, k, (uint32_t)a, kTagWLC), z);
+            for (int e = 0; e < 4 && 4 * q + e <= N; ++e) NZ[a * Q + 4 * q + e] = amp * z[e];
+        }
+        for (int n = 1 + t; n <= N; n += 64)
+            for (int a = 0; a < 3; ++a) UN[a * P + n] = U[a * P + n];
+        __syncthreads();
+        for (int it = 0; it < iters; ++it) {
+            for (int n = 1 + t; n <= N; n += 64) {  // midpoint bonds
+                double w[3], s2 = 0.0;
+                for (int a = 0; a < 3; ++a) {
+                    w[a] = U[a * P + n] + UN[a * P + n];
+                    s2 += w[a] * w[a];
+                }
+                const double inv = 1.0 / sqrt(s2);
+                for (int a = 0; a < 3; ++a) UM[a * P + n] = w[a] * inv;
+            }
+            __syncthreads();
+            for (int n = t; n <= N; n += 64)  // regular displacements of the beads
+                for (int a = 0; a < 3; ++a) {
+                    const double *um = UM + a * P;
+                    const double hn = n >= 1 ? -(um[n - 1] + um[n + 1]) : 0.0;
+                    const double hn1 = n + 1 <= N ? -(um[n] + um[n + 2]) : 0.0;
+                    D[a * Q + n] = (hn1 - hn) * dt + NZ[a * Q + n];
+                }
+            __syncthreads();
+            for (int n = 1 + t; n <= N; n += 64) {  // row n: a f_{n-1} + b f_n + c f_{n+1} = r
+                double wl = 0.0, wm = 0.0, wr = 0.0, wd = 0.0;
+                for (int a = 0; a < 3; ++a) {
+                    const double w = U[a * P + n] + UN[a * P + n];
+                    wl += w * UM[a * P + n - 1];
+                    wm += w * UM[a * P + n];
+                    wr += w * UM[a * P + n + 1];
+                    wd += w * (D[a * Q + n] - D[a * Q + n - 1]);
+                }
+                rows[n - 1] = wl * dt;
+                rows[N + n - 1] = -2.0 * wm * dt;
+                rows[2 * N + n - 1] = wr * dt;
+                rows[3 * N + n - 1] = -wd;
+            }
+            __syncthreads();
+            int h = 0;
+            for (int sd = 1; sd < N; sd *= 2, h ^= 1) {
+                const double *ra = rows + (size_t)(4 * h) * N, *rb = ra + N, *rc = rb + N,
+                             *rr = rc + N;
+                double *oa = rows + (size_t)(4 * (h ^ 1)) * N, *ob = oa + N, *oc = ob + N,
+                       *od = oc + N;
+                for (int j = t; j < N; j += 64) {
+                    double an = 0.0, cn = 0.0, bn = rb[j], dn = rr[j];
+                    if (j - sd >= 0) {
+                        const double al = -ra[j] / rb[j - sd];
+                        an = al * ra[j - sd];
+                        bn += al * rc[j - sd];
+                        dn += al * rr[j - sd];
+                    }
+                    if (j + sd < N) {
+                        const double ga = -rc[j] / rb[j + sd];
+                        cn = ga * rc[j + sd];
+                        bn += ga * ra[j + sd];
+                        dn += ga * rr[j + sd];
+                    }
+                    oa[j] = an;
+                    ob[j] = bn;
+                    oc[j] = cn;
+                    od[j] = dn;
+                }
+                __syncthreads();
+            }
+            for (int j = t; j < N; j += 64)
+                F[j + 1] = rows[(size_t)(4 * h + 3) * N + j] / rows[(size_t)(4 * h + 1) * N + j];
+            __syncthreads();
+            double change = 0.0;
+            for (int n = 1 + t; n <= N; n += 64) {  // bond update
+                const double fl = F[n - 1], fm = F[n], fr = F[n + 1];
+                for (int a = 0; a < 3; ++a) {
+                    const double v = U[a * P + n] + (D[a * Q + n] - D[a * Q + n - 1]) +
+                                     (fl * UM[a * P + n - 1] - 2.0 * fm * UM[a * P + n] +
+                                      fr * UM[a * P + n + 1]) * dt;
+                    change = fmax(change, fabs(v - UN[a * P + n]));
+                    UN[a * P + n] = v;
+                }
+            }
+            __syncthreads();
+            if (tol > 0.0) {  // the same maximum in every lane: a uniform exit
+                for (int o = 32; o >= 1; o >>= 1) change = fmax(change, __shfl_xor(change, o));
+                if (change <= tol) break;
+            }
+        }
+        if (t < 3) r0 += D[t * Q] + F[1] * UM[t * P + 1] * dt;
+        for (int n = 1 + t; n <= N; n += 64)
+            for (int a = 0; a < 3; ++a) U[a * P + n] = UN[a * P + n];
+        __syncthreads();
+    }
+    if (t < 3) {
+        double v = r0;
+        x[t * M] = v;
+        for (int n = 1; n <= N; ++n) {
+            v += U[t * P + n];
+            x[t * M + n] = v;
+        }
+    }
 }
 
 __global__ void reduce_chains_kernel(const double *__restrict__ acc, double *__restrict__ out,
@@ -631,18 +790,26 @@ hipError_t launch_euler_f64(double *pos, const int32_t *ids, int M, int nch, dou
 
 size_t wlc_scratch_doubles(int M, int nch)
 {
+    if (sizeof(double) * wlc_lds_doubles(M) <= kWlcMaxLds) return 0;  // chain held in LDS
     const size_t N = (size_t)M - 1;
     return (9 * (N + 2) + 3 * (N + 1) + 2 * N + (N + 2)) * (size_t)nch;
 }
 
 hipError_t launch_wlc(double *pos, double *scr, const int32_t *ids, int M, int nch, double T_bar,
-                      double dt, int iters, uint64_t seed, int64_t step0, int n_steps,
-                      hipStream_t st)
+                      double dt, int iters, double tol, uint64_t seed, int64_t step0,
+                      int n_steps, hipStream_t st)
 {
     if (nch == 0 || n_steps == 0) return hipSuccess;
     if (M < 2 || iters < 1) return hipErrorInvalidValue;
+    const size_t lds = sizeof(double) * wlc_lds_doubles(M);
+    if (lds <= kWlcMaxLds) {
+        hipLaunchKernelGGL(wlc_wave_kernel, dim3(nch), dim3(64), lds, st, pos, ids, M, T_bar, dt,
+                           iters, tol, seed, step0, n_steps);
+        return hipGetLastError();
+    }
+    if (!scr) return hipErrorInvalidValue;
     hipLaunchKernelGGL(wlc_kernel, dim3((nch + 63) / 64), dim3(64), 0, st, pos, scr, ids, M, nch,
-                       T_bar, dt, iters, seed, step0, n_steps);
+                       T_bar, dt, iters, tol, seed, step0, n_steps);
     return hipGetLastError();
 }
 

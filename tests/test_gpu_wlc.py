@@ -1,6 +1,8 @@
 """The nu -> 0 (inextensible wormlike chain) limit on the GPU, dm_step_wlc,
 against the oracle on identical Philox streams (FP64 both: trajectories agree
-to rounding), and the unit bond lengths it maintains."""
+to rounding; the cyclic-reduction tension solve rounds differently from the
+oracle's Thomas sweep, by ~1e-15 relative), and the unit bond lengths it
+maintains."""
 import numpy as np
 import pytest
 import torch
@@ -20,14 +22,33 @@ def _device():
     torch.cuda.synchronize()
 
 
-@pytest.mark.parametrize("M", [2, 3, 17, 100])
+@pytest.mark.parametrize("M", [2, 3, 17, 65, 66, 100, 341, 342])
 def test_wlc_matches_oracle(M):
+    """Up to M = 341 one wavefront per chain (bonds over the lanes, several per
+    lane from M = 66, tensions by cyclic reduction); from M = 342 the chain
+    no longer fits the LDS and one thread per chain runs the Thomas sweep."""
     B, T, dt, n = 7, 0.2, 2e-3, 150
     pos = unit_chains(B, M, M)
     with Context(pos, seed=12, precision="fp64") as ctx:
         ctx.step_wlc(n, dt, T, iters=8)
         got = ctx.positions()
     want = oracle.step_wlc(pos, T, dt, n, iters=8, seed=12)
+    err = np.abs(got - want).max() / max(1.0, M - 1)
+    print(f"M={M}: max |dr| / (M-1) = {err:.2e}")
+    assert err < 1e-10
+
+
+@pytest.mark.parametrize("M", [64, 342])
+def test_wlc_converged_cycles_match_oracle(M):
+    """The cycle stopped at convergence (tol 1e-12, at most 16 passes) on both
+    sides: a pass count that differs near the threshold moves a bond by at
+    most ~tol, far inside the parity bound."""
+    B, T, dt, n = 9, 1.0 / 114.4, 1e-3, 200
+    pos = unit_chains(B, M, 3 * M, T_bar=T)
+    with Context(pos, seed=4, precision="fp64") as ctx:
+        ctx.step_wlc(n, dt, T, iters=16, tol=1e-12)
+        got = ctx.positions()
+    want = oracle.step_wlc(pos, T, dt, n, iters=16, seed=4, tol=1e-12)
     err = np.abs(got - want).max() / max(1.0, M - 1)
     print(f"M={M}: max |dr| / (M-1) = {err:.2e}")
     assert err < 1e-10

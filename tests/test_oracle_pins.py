@@ -612,6 +612,20 @@ def test_wlc_keeps_unit_bonds():
     assert np.abs(np.linalg.norm(np.diff(x, axis=2), axis=1) - 1).max() < 1e-9
 
 
+def test_wlc_cycle_converges_to_its_fixed_point():
+    """Iterating the cycle until no bond component moves by more than 1e-13
+    (the paper iterates to convergence) reaches the fixed point that 30 fixed
+    passes reach, and holds unit bonds; a single pass (the explicit first
+    guess u' = u) does not."""
+    x0 = _unit_chains(10, 12, 9)
+    ref = oracle.step_wlc(x0, 0.1, 2e-3, 300, iters=30, seed=3)
+    conv = oracle.step_wlc(x0, 0.1, 2e-3, 300, iters=30, seed=3, tol=1e-13)
+    one = oracle.step_wlc(x0, 0.1, 2e-3, 300, iters=1, seed=3)
+    assert np.abs(conv - ref).max() < 1e-11
+    assert np.abs(np.linalg.norm(np.diff(conv, axis=2), axis=1) - 1).max() < 1e-12
+    assert np.abs(np.linalg.norm(np.diff(one, axis=2), axis=1) - 1).max() > 1e-6
+
+
 def test_wlc_dumbbell_rotational_diffusion():
     """One rigid bond between two unit-friction beads: the orientation
     diffuses with D_r = 2 T-bar, so <u(t).u(0)> = exp(-4 T-bar t)."""
