@@ -161,7 +161,11 @@ typedef struct {
     int32_t use_graphs;      /* fused paths with sample_every > 0, 1: whole
                                 sampling blocks (the fused launch, the step
                                 counter and the observables) are captured
-                                once as a HIP graph and replayed */
+                                once as a HIP graph and replayed.  When the
+                                launch leaves compute units idle, runs of
+                                several blocks take each block's sample from
+                                a snapshot of its state on a second stream
+                                while the next block runs (same results) */
     int32_t tiles_per_wg;    /* fused paths: 0 = automatic; 1..4 = tiles of 5
                                 chains per workgroup where the tables are
                                 resident (streamed tables always take 4) */

@@ -80,6 +80,16 @@ struct dm_ctx {
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     int graph_steps = 0;
+    // deferred observables: runs of several sampling blocks replay "first"
+    // (launch, snapshot of the state, counter advance) and then "steady",
+    // where the observables of the previous block's snapshot run on a second
+    // stream beside the launch, on the compute units the launch leaves idle
+    hipStream_t cap_stream2 = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    hipGraph_t g_first = nullptr, g_steady = nullptr;
+    hipGraphExec_t x_first = nullptr, x_steady = nullptr;
+    int overlap_steps = 0;
+    int ncu = 0;
     std::string tune_report;
     std::string err;
 };
@@ -145,14 +155,16 @@ int bucket_positions(dm_ctx *ctx, Bucket &b, hipStream_t st)
 // Observables of the current state; with accumulate != 0 also the sums and
 // the tumbling state, at the step held in ctx->d_step (set here unless the
 // call is being captured, where the block's own counter kernel keeps it).
-int observe(dm_ctx *ctx, int accumulate, hipStream_t st, bool captured = false)
+int observe(dm_ctx *ctx, int accumulate, hipStream_t st, bool captured = false,
+            bool from_snapshot = false, int max_wg = 0)
 {
     if (accumulate && !captured) DM_HIP(ctx, dm::fused_set_step(ctx->d_step, ctx->step, st));
     for (Bucket &b : ctx->buckets) {
         if (fused_precision(ctx->precision)) {
             DM_HIP(ctx, dm::fused_observe(b.fused, b.M, b.d_obs, b.d_m2, b.d_acc, b.d_cm0,
                                           b.d_tumble, b.d_tumble + b.n, ctx->d_step, b.d_ring,
-                                          b.d_ccount, ctx->corr_lags, accumulate, st));
+                                          b.d_ccount, ctx->corr_lags, accumulate, st,
+                                          from_snapshot, max_wg));
             continue;
         }
         int rc = bucket_positions(ctx, b, st);
@@ -164,7 +176,7 @@ int observe(dm_ctx *ctx, int accumulate, hipStream_t st, bool captured = false)
     return DM_OK;
 }
 
-void drop_graph(dm_ctx *ctx)
+void drop_block_graph(dm_ctx *ctx)
 {
     if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
     if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
@@ -173,12 +185,92 @@ void drop_graph(dm_ctx *ctx)
     ctx->graph_steps = 0;
 }
 
+void drop_overlap_graphs(dm_ctx *ctx)
+{
+    for (hipGraphExec_t *x : {&ctx->x_first, &ctx->x_steady})
+        if (*x) (void)hipGraphExecDestroy(*x), *x = nullptr;
+    for (hipGraph_t *g : {&ctx->g_first, &ctx->g_steady})
+        if (*g) (void)hipGraphDestroy(*g), *g = nullptr;
+    ctx->overlap_steps = 0;
+}
+
+void drop_graph(dm_ctx *ctx)
+{
+    drop_block_graph(ctx);
+    drop_overlap_graphs(ctx);
+}
+
+// Workgroups of a deferred observation kernel: few enough that a launch
+// whose items fit the remaining compute units is never kept waiting.
+constexpr int kObsWorkgroups = 40;
+
+// Deferred observables pay off when the launch leaves compute units idle:
+// one workgroup item per compute unit, all in flight at once.
+bool overlap_allowed(const dm_ctx *ctx)
+{
+    return ctx->ncu > 0 && ctx->plan.nitems + kObsWorkgroups <= ctx->ncu;
+}
+
+// Capture the two graphs of deferred observables (see dm_ctx).
+int capture_overlap(dm_ctx *ctx, int steps)
+{
+    drop_overlap_graphs(ctx);
+    for (Bucket &b : ctx->buckets) DM_HIP(ctx, dm::fused_snapshot_alloc(b.fused));
+    if (!ctx->cap_stream)
+        DM_HIP(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+    if (!ctx->cap_stream2)
+        DM_HIP(ctx, hipStreamCreateWithFlags(&ctx->cap_stream2, hipStreamNonBlocking));
+    if (!ctx->ev_fork) DM_HIP(ctx, hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming));
+    if (!ctx->ev_join) DM_HIP(ctx, hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming));
+    hipStream_t s1 = ctx->cap_stream, s2 = ctx->cap_stream2;
+    for (int which = 0; which < 2; ++which) {
+        DM_HIP(ctx, hipStreamBeginCapture(s1, hipStreamCaptureModeThreadLocal));
+        hipError_t e = hipSuccess;
+        int rc = DM_OK;
+        if (which == 1) {  // the previous block's sample beside this block's launch
+            e = hipEventRecord(ctx->ev_fork, s1);
+            if (e == hipSuccess) e = hipStreamWaitEvent(s2, ctx->ev_fork, 0);
+            if (e == hipSuccess) rc = observe(ctx, 1, s2, true, true, kObsWorkgroups);
+        }
+        if (e == hipSuccess && rc == DM_OK)
+            e = dm::fused_launch(ctx->plan, ctx->seed, 0, ctx->d_step, steps, ctx->nonlinear, s1);
+        if (which == 1) {
+            const hipError_t e1 = hipEventRecord(ctx->ev_join, s2);
+            const hipError_t e2 = e1 == hipSuccess ? hipStreamWaitEvent(s1, ctx->ev_join, 0) : e1;
+            if (e == hipSuccess) e = e2;
+        }
+        for (Bucket &b : ctx->buckets)
+            if (e == hipSuccess) e = dm::fused_snapshot(b.fused, s1);
+        if (e == hipSuccess) e = dm::fused_advance_step(ctx->d_step, steps, s1);
+        hipGraph_t g = nullptr;
+        const hipError_t ec = hipStreamEndCapture(s1, &g);
+        if (e != hipSuccess || rc != DM_OK || ec != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            drop_overlap_graphs(ctx);
+            if (rc != DM_OK) return rc;
+            return fail(ctx, DM_EHIP, "graph capture failed: %s",
+                        hipGetErrorString(e != hipSuccess ? e : ec));
+        }
+        hipGraphExec_t x = nullptr;
+        e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(g);
+            drop_overlap_graphs(ctx);
+            return fail(ctx, DM_EHIP, "hipGraphInstantiate failed: %s", hipGetErrorString(e));
+        }
+        (which ? ctx->g_steady : ctx->g_first) = g;
+        (which ? ctx->x_steady : ctx->x_first) = x;
+    }
+    ctx->overlap_steps = steps;
+    return DM_OK;
+}
+
 // Capture one sampling block of `steps` fused steps: the launch reads its
 // Philox step from ctx->d_step, a one-thread kernel advances it, then the
 // observables are accumulated.  No memset nodes (plain kernels only).
 int capture_block(dm_ctx *ctx, int steps)
 {
-    drop_graph(ctx);
+    drop_block_graph(ctx);
     if (!ctx->cap_stream)
         DM_HIP(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
     DM_HIP(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
@@ -282,6 +374,9 @@ int dm_init_chains(dm_ctx **out, int32_t n_chains, const int32_t *beads, const d
         delete ctx;
         return fail(nullptr, DM_EHIP, "no HIP device");
     }
+    if (hipDeviceGetAttribute(&ctx->ncu, hipDeviceAttributeMultiprocessorCount, ctx->device) !=
+        hipSuccess)
+        ctx->ncu = 0;  // deferred observables off
     ctx->beads.assign(beads, beads + n_chains);
     ctx->offset.resize(n_chains);
     int64_t off = 0;
@@ -493,12 +588,29 @@ int dm_step_modes(dm_ctx *ctx, int64_t n_steps)
     while (done < n_steps) {
         const int se = ctx->sample_every;
         if (graphs && ctx->step % se == 0 && n_steps - done >= se) {
+            const int64_t blocks = (n_steps - done) / se;
+            if (blocks >= 2 && overlap_allowed(ctx)) {
+                // deferred observables: each block's sample is taken from its
+                // snapshot during the next block; the last one right after
+                if (!ctx->x_steady || ctx->overlap_steps != se) {
+                    int rc = capture_overlap(ctx, se);
+                    if (rc) return rc;
+                }
+                DM_HIP(ctx, dm::fused_set_step(ctx->d_step, ctx->step, ctx->stream));
+                DM_HIP(ctx, hipGraphLaunch(ctx->x_first, ctx->stream));
+                for (int64_t i = 1; i < blocks; ++i)
+                    DM_HIP(ctx, hipGraphLaunch(ctx->x_steady, ctx->stream));
+                ctx->step += blocks * se;
+                done += blocks * se;
+                int rc = observe(ctx, 1, ctx->stream, false, true);
+                if (rc) return rc;
+                continue;
+            }
             // whole sampling blocks: replay the captured block
             if (!ctx->graph_exec || ctx->graph_steps != se) {
                 int rc = capture_block(ctx, se);
                 if (rc) return rc;
             }
-            const int64_t blocks = (n_steps - done) / se;
             DM_HIP(ctx, dm::fused_set_step(ctx->d_step, ctx->step, ctx->stream));
             for (int64_t i = 0; i < blocks; ++i)
                 DM_HIP(ctx, hipGraphLaunch(ctx->graph_exec, ctx->stream));
@@ -884,6 +996,9 @@ int dm_destroy(dm_ctx *ctx)
     (void)hipStreamSynchronize(ctx->stream);
     drop_graph(ctx);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+    if (ctx->cap_stream2) (void)hipStreamDestroy(ctx->cap_stream2);
+    if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
+    if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
     dm::fused_plan_free(ctx->plan);
     for (Bucket &b : ctx->buckets) free_bucket(b);
     if (ctx->d_flag) (void)hipFree(ctx->d_flag);

@@ -21,6 +21,8 @@ struct FusedBucket {
     float *d_coef = nullptr; // per-slot update coefficients (see dm_fused.hip)
     double *d_sig = nullptr; // sigma_p of the even modes, by half-mode slot
     float *d_P = nullptr;    // FP32 position tables of the observables
+    float *d_Rs = nullptr;   // snapshot of d_R / d_R0 for deferred observables
+    double *d_R0s = nullptr;
     int JC = 0;              // coupling row tiles with non-negligible C_p
     int resident = 0;        // tables held in LDS for the whole launch
     int tpw = 4;             // tiles per workgroup (1..4; 4 when streamed)
@@ -70,10 +72,18 @@ hipError_t fused_advance_step(int64_t *d_step, int64_t n, hipStream_t st);
 // Per-chain observables, |R_p|^2 and (accumulate != 0) the FP64 accumulators
 // and tumbling state of the bucket, in the layout of launch_chain_obs, from
 // the fused state directly (positions in FP32 MFMA, sums in FP64).
+// from_snapshot: read the state saved by fused_snapshot instead of the live
+// one; max_wg > 0 caps the grid (each workgroup then loops over tiles).
 hipError_t fused_observe(const FusedBucket &f, int M, double *obs, double *m2, double *acc,
                          const double *cm0, double *tstate, double *tlast,
                          const int64_t *d_step, double *ring, double *ccount, int K,
-                         int accumulate, hipStream_t st);
+                         int accumulate, hipStream_t st, bool from_snapshot = false,
+                         int max_wg = 0);
+// Copy of the state (d_R, d_R0 -> d_Rs, d_R0s) for observables taken while
+// the next steps already run; fused_snapshot_alloc allocates it (not inside a
+// graph capture).
+hipError_t fused_snapshot_alloc(FusedBucket &f);
+hipError_t fused_snapshot(const FusedBucket &f, hipStream_t st);
 hipError_t fused_check_finite(const FusedBucket &f, int M, int n, int *flag, hipStream_t st);
 
 }  // namespace dm

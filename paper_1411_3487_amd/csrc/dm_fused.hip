@@ -610,14 +610,14 @@ struct ObsArgs {
     double *tstate, *tlast;
     const int64_t *step;
     double *ring, *ccount;
-    int K, M, n, accumulate;
+    int K, M, n, ntiles, accumulate;
 };
 
+// Observables of one tile (pos: [16][M] floats of LDS).
 template <int RT>
-__global__ __launch_bounds__(256) void fused_obs_kernel(ObsArgs a)
+__device__ __forceinline__ void obs_tile(const ObsArgs &a, int tile, float *pos)
 {
-    extern __shared__ float pos[];  // [16][M]
-    const int M = a.M, H = M / 2, tile = blockIdx.x;
+    const int M = a.M, H = M / 2;
     const int lane = threadIdx.x & 63, col = lane & 15, g = lane >> 4;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int cl = col / 3, alpha = col - 3 * cl;
@@ -762,6 +762,29 @@ __global__ __launch_bounds__(256) void fused_obs_kernel(ObsArgs a)
         corr_update(a.ring + c * ((size_t)9 << (a.K - 1)), a.ccount + c,
                     ac + DM_NACC_HEAD + M + DM_NTUMBLE_BINS, v, a.K);
     }
+}
+
+// One workgroup per tile, or a smaller grid looping over the tiles (to leave
+// most compute units to a fused launch running at the same time).
+template <int RT>
+__global__ __launch_bounds__(256) void fused_obs_kernel(ObsArgs a)
+{
+    extern __shared__ float pos[];  // [16][M]
+    for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
+        obs_tile<RT>(a, tile, pos);
+        __syncthreads();  // pos is rewritten for the next tile
+    }
+}
+
+__global__ void snapshot_kernel(const f32x4 *__restrict__ R, f32x4 *__restrict__ Rs, size_t n4,
+                                const double *__restrict__ R0, double *__restrict__ R0s,
+                                size_t n0)
+{
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride)
+        Rs[i] = R[i];
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n0; i += stride)
+        R0s[i] = R0[i];
 }
 
 // FP64 amplitudes [chain][component][p] -> fused state (even modes scaled
@@ -975,6 +998,8 @@ void fused_free(FusedBucket &f)
     if (f.d_coef) (void)hipFree(f.d_coef);
     if (f.d_sig) (void)hipFree(f.d_sig);
     if (f.d_P) (void)hipFree(f.d_P);
+    if (f.d_Rs) (void)hipFree(f.d_Rs);
+    if (f.d_R0s) (void)hipFree(f.d_R0s);
     f = FusedBucket();
 }
 
@@ -1345,21 +1370,44 @@ hipError_t fused_advance_step(int64_t *d_step, int64_t n, hipStream_t st)
 }
 
 template <int RT>
-static void launch_obs(const ObsArgs &a, int ntiles, hipStream_t st)
+static void launch_obs(const ObsArgs &a, int nwg, hipStream_t st)
 {
-    hipLaunchKernelGGL(fused_obs_kernel<RT>, dim3(ntiles), dim3(256),
+    hipLaunchKernelGGL(fused_obs_kernel<RT>, dim3(nwg), dim3(256),
                        sizeof(float) * 16 * (size_t)a.M, st, a);
+}
+
+hipError_t fused_snapshot_alloc(FusedBucket &f)
+{
+    hipError_t e = hipSuccess;
+    if (!f.d_Rs) e = hipMalloc((void **)&f.d_Rs, sizeof(float) * state_floats(f.RT, f.ntiles));
+    if (e == hipSuccess && !f.d_R0s)
+        e = hipMalloc((void **)&f.d_R0s, sizeof(double) * 16 * (size_t)f.ntiles);
+    return e;
+}
+
+hipError_t fused_snapshot(const FusedBucket &f, hipStream_t st)
+{
+    if (f.n <= 0) return hipSuccess;
+    if (!f.d_Rs || !f.d_R0s) return hipErrorInvalidValue;
+    const size_t n4 = state_floats(f.RT, f.ntiles) / 4, n0 = (size_t)16 * f.ntiles;
+    unsigned b = nblocks(n4, 256);
+    if (b > 1024) b = 1024;
+    hipLaunchKernelGGL(snapshot_kernel, dim3(b), dim3(256), 0, st,
+                       reinterpret_cast<const f32x4 *>(f.d_R), reinterpret_cast<f32x4 *>(f.d_Rs),
+                       n4, f.d_R0, f.d_R0s, n0);
+    return hipGetLastError();
 }
 
 hipError_t fused_observe(const FusedBucket &f, int M, double *obs, double *m2, double *acc,
                          const double *cm0, double *tstate, double *tlast,
                          const int64_t *d_step, double *ring, double *ccount, int K,
-                         int accumulate, hipStream_t st)
+                         int accumulate, hipStream_t st, bool from_snapshot, int max_wg)
 {
     if (f.n <= 0) return hipSuccess;
+    if (from_snapshot && (!f.d_Rs || !f.d_R0s)) return hipErrorInvalidValue;
     ObsArgs a;
-    a.R = f.d_R;
-    a.R0 = f.d_R0;
+    a.R = from_snapshot ? f.d_Rs : f.d_R;
+    a.R0 = from_snapshot ? f.d_R0s : f.d_R0;
     a.P = f.d_P;
     a.sig = f.d_sig;
     a.obs = obs;
@@ -1374,16 +1422,18 @@ hipError_t fused_observe(const FusedBucket &f, int M, double *obs, double *m2, d
     a.K = K;
     a.M = M;
     a.n = f.n;
+    a.ntiles = f.ntiles;
     a.accumulate = accumulate;
+    const int nwg = max_wg > 0 ? std::min(f.ntiles, max_wg) : f.ntiles;
     switch (f.RT) {
-    case 2: launch_obs<2>(a, f.ntiles, st); break;
-    case 4: launch_obs<4>(a, f.ntiles, st); break;
-    case 6: launch_obs<6>(a, f.ntiles, st); break;
-    case 8: launch_obs<8>(a, f.ntiles, st); break;
-    case 10: launch_obs<10>(a, f.ntiles, st); break;
-    case 12: launch_obs<12>(a, f.ntiles, st); break;
-    case 14: launch_obs<14>(a, f.ntiles, st); break;
-    case 16: launch_obs<16>(a, f.ntiles, st); break;
+    case 2: launch_obs<2>(a, nwg, st); break;
+    case 4: launch_obs<4>(a, nwg, st); break;
+    case 6: launch_obs<6>(a, nwg, st); break;
+    case 8: launch_obs<8>(a, nwg, st); break;
+    case 10: launch_obs<10>(a, nwg, st); break;
+    case 12: launch_obs<12>(a, nwg, st); break;
+    case 14: launch_obs<14>(a, nwg, st); break;
+    case 16: launch_obs<16>(a, nwg, st); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
