@@ -90,6 +90,9 @@ struct dm_ctx {
     hipGraphExec_t x_first = nullptr, x_steady = nullptr;
     int overlap_steps = 0;
     int ncu = 0;
+    int obs_wg = 0;      // grid cap of the deferred observation kernels
+    int ov_se = 0;       // sampling interval the overlap decision was taken for
+    bool ov_use = false; // that decision
     std::string tune_report;
     std::string err;
 };
@@ -198,17 +201,50 @@ void drop_graph(dm_ctx *ctx)
 {
     drop_block_graph(ctx);
     drop_overlap_graphs(ctx);
+    ctx->ov_se = 0;  // the overlap decision depends on the plan
 }
 
-// Workgroups of a deferred observation kernel: few enough that a launch
-// whose items fit the remaining compute units is never kept waiting.
-constexpr int kObsWorkgroups = 40;
-
-// Deferred observables pay off when the launch leaves compute units idle:
-// one workgroup item per compute unit, all in flight at once.
-bool overlap_allowed(const dm_ctx *ctx)
+// Deferred observables pay off when the launch leaves compute units idle
+// (one workgroup item per compute unit, all in flight at once, at least 16
+// units to spare: the observation kernels are capped to the spare units
+// less 3, so the launch's items never wait for them) and when the capped
+// observation is not slower than the block it hides behind: it is timed
+// once per sampling interval on the live state without accumulating (that
+// rewrites only the current-state observables, with the same values), and
+// compared with the block's estimated time (the longest item's step time,
+// measured by the autotuner or modelled, times the steps per block).
+int overlap_pays(dm_ctx *ctx, int se, bool *use)
 {
-    return ctx->ncu > 0 && ctx->plan.nitems + kObsWorkgroups <= ctx->ncu;
+    if (ctx->ov_se == se) {
+        *use = ctx->ov_use;
+        return DM_OK;
+    }
+    const int spare = ctx->ncu - ctx->plan.nitems - 3;
+    ctx->ov_se = se;
+    ctx->ov_use = false;
+    if (ctx->ncu > 0 && spare >= 16) {
+        ctx->obs_wg = spare;
+        double step_us = 0.0;
+        for (Bucket &b : ctx->buckets) step_us = std::max(step_us, dm::fused_item_us(b.fused));
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        DM_HIP(ctx, hipEventCreate(&e0));
+        hipError_t e = hipEventCreate(&e1);
+        int rc = DM_OK;
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventRecord(e0, ctx->stream);
+        if (e == hipSuccess) rc = observe(ctx, 0, ctx->stream, false, false, ctx->obs_wg);
+        if (e == hipSuccess && rc == DM_OK) e = hipEventRecord(e1, ctx->stream);
+        if (e == hipSuccess && rc == DM_OK) e = hipEventSynchronize(e1);
+        if (e == hipSuccess && rc == DM_OK) e = hipEventElapsedTime(&ms, e0, e1);
+        (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        if (rc != DM_OK) return rc;
+        if (e != hipSuccess)
+            return fail(ctx, DM_EHIP, "timing the observables failed: %s", hipGetErrorString(e));
+        ctx->ov_use = 1e3 * ms <= step_us * se;
+    }
+    *use = ctx->ov_use;
+    return DM_OK;
 }
 
 // Capture the two graphs of deferred observables (see dm_ctx).
@@ -230,7 +266,7 @@ int capture_overlap(dm_ctx *ctx, int steps)
         if (which == 1) {  // the previous block's sample beside this block's launch
             e = hipEventRecord(ctx->ev_fork, s1);
             if (e == hipSuccess) e = hipStreamWaitEvent(s2, ctx->ev_fork, 0);
-            if (e == hipSuccess) rc = observe(ctx, 1, s2, true, true, kObsWorkgroups);
+            if (e == hipSuccess) rc = observe(ctx, 1, s2, true, true, ctx->obs_wg);
         }
         if (e == hipSuccess && rc == DM_OK)
             e = dm::fused_launch(ctx->plan, ctx->seed, 0, ctx->d_step, steps, ctx->nonlinear, s1);
@@ -589,7 +625,12 @@ int dm_step_modes(dm_ctx *ctx, int64_t n_steps)
         const int se = ctx->sample_every;
         if (graphs && ctx->step % se == 0 && n_steps - done >= se) {
             const int64_t blocks = (n_steps - done) / se;
-            if (blocks >= 2 && overlap_allowed(ctx)) {
+            bool overlap = false;
+            if (blocks >= 2) {
+                int rc = overlap_pays(ctx, se, &overlap);
+                if (rc) return rc;
+            }
+            if (overlap) {
                 // deferred observables: each block's sample is taken from its
                 // snapshot during the next block; the last one right after
                 if (!ctx->x_steady || ctx->overlap_steps != se) {

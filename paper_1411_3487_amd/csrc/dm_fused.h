@@ -63,6 +63,9 @@ hipError_t fused_launch(const FusedPlan &p, uint64_t seed, int64_t step0, const 
 // per candidate goes to report.
 hipError_t fused_autotune(std::vector<FusedBucket *> &bs, uint64_t seed, int steps,
                           hipStream_t st, std::string &report);
+// Time of one workgroup item of the bucket for one step, in microseconds:
+// measured by the autotuner, else the cost model.
+double fused_item_us(const FusedBucket &f);
 // Force a tile shape where it exists: table_mode 1 resident, 2 streamed (0
 // keeps the current); tpw 1..4 where resident (0 keeps the current).
 void fused_force_shape(FusedBucket &f, int table_mode, int tpw);

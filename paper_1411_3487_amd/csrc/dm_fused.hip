@@ -1095,6 +1095,8 @@ static double model_us(const FusedBucket &f)
     return 0.12 * rt * rt + 0.3 * rt + (f.resident ? 0.0 : 0.02 * rt * rt);
 }
 
+double fused_item_us(const FusedBucket &f) { return f.item_us > 0.0 ? f.item_us : model_us(f); }
+
 // Items of the given buckets, longest first (ties in bucket, tile order).
 static std::vector<Item> ordered_items(const std::vector<const FusedBucket *> &bs,
                                        std::vector<double> *cost = nullptr)
