@@ -311,14 +311,24 @@ __device__ __forceinline__ void fused_tiles(const BucketArgs &a, const LaunchArg
 
     // Streaming: issue the copy of stage t + DIST (of this step or, wrapping,
     // of the next) and, after the compute of stage t, wait until stage t + 1
-    // has landed (loads retire in order).
+    // has landed (loads retire in order).  The tests below read ns, which
+    // the step loop makes opaque at every step: otherwise the compiler
+    // hoists one test per stage out of the loop, the longest shapes spill
+    // them, and each reload from scratch (a vector memory load, counted with
+    // the copies in flight) waits for all the prefetched stages.
+    int ns = NS;
     auto prefetch = [&](int t, int s) {
         if constexpr (!RESIDENT) {
             // stage t + DIST counted from the start of this step, as (step
-            // ahead, stage of that step); nothing beyond the last step
+            // ahead, stage of that step); nothing beyond the last step.
+            // DIST <= RT <= NS, so it is at most one step ahead (a compare,
+            // not a scalar division by the run-time NS).
+            static_assert(RESIDENT || DIST <= RT, "prefetch reaches two steps ahead");
             const int tn = t + DIST;
-            if (s + tn / NS < la.n_steps)
-                stage<SF>(xrs, (tn % NS) * SF, xb + ((b0 + tn) % NB) * SF * 64, wave, lane_bytes);
+            const bool ahead = tn >= ns;
+            if (s + (ahead ? 1 : 0) < la.n_steps)
+                stage<SF>(xrs, (ahead ? tn - ns : tn) * SF, xb + ((b0 + tn) % NB) * SF * 64, wave,
+                          lane_bytes);
         }
     };
     // outstanding loads of this wave after stage t: stages t+1 .. t+DIST that
@@ -326,13 +336,24 @@ __device__ __forceinline__ void fused_tiles(const BucketArgs &a, const LaunchArg
     auto finish = [&](int t, int s) {
         if constexpr (!RESIDENT) {
             // last stage issued so far, counted from the start of this step
-            const int last = min(t + DIST, (la.n_steps - s) * NS - 1);
+            const int last = min(t + DIST, (la.n_steps - s) * ns - 1);
             const int ahead = last - (t + 1);  // issued beyond t+1
             if (ahead >= DIST - 1)
                 wait_vmcnt<(DIST - 1) * (SF / 4)>();
             else
                 wait_vmcnt<0>();
-            __syncthreads();
+            // A bare barrier: __syncthreads() would add a workgroup release
+            // fence, i.e. a wait for ALL outstanding loads (vmcnt(0)), which
+            // drains the prefetch pipeline at every stage.  The explicit wait
+            // above has made this wave's copies of stage t+1 land in LDS; the
+            // barrier makes that true for every wave.  The buffer the next
+            // prefetch overwrites held stage t-1, whose LDS reads every wave
+            // consumed (its products need them) before reaching this point.
+            // The signal fences keep the compiler from moving LDS accesses
+            // across the barrier; they emit no instruction.
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
+            __builtin_amdgcn_s_barrier();
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
         }
     };
     auto stage_at = [&](int t) -> const f32x4 * {
@@ -343,6 +364,10 @@ __device__ __forceinline__ void fused_tiles(const BucketArgs &a, const LaunchArg
     };
     for (int s = 0; s < la.n_steps; ++s) {
         const int64_t k = step0 + s;
+        if constexpr (!RESIDENT) {
+            ns = NS;
+            asm volatile("" : "+s"(ns));
+        }
         f32x4 Gp[RT], Gm[RT];
         [[maybe_unused]] bf16x8 gph[KS], gpl[KS], gmh[KS], gml[KS];
         if (la.nonlinear) {
@@ -364,32 +389,41 @@ __device__ __forceinline__ void fused_tiles(const BucketArgs &a, const LaunchArg
                         split_bf16(Ro[2 * q], Ro[2 * q + 1], boh, bol);
                         split_bf16(Re[2 * q], Re[2 * q + 1], beh, bel);
                     }
-                    // all fragments of the half slab first, then each product over
-                    // the HALF row tiles: HALF independent accumulator pairs between
-                    // two MFMAs into the same accumulator
-                    bf16x8 xoh[HALF], xol[HALF], xeh[HALF], xel[HALF];
+                    // the fragments of FB row tiles first, then each product over
+                    // them: FB independent accumulator pairs between two MFMAs
+                    // into the same accumulator (FB = HALF up to RT = 12; the
+                    // longest shapes take 4 at a time, whose 64 registers instead
+                    // of 4 HALF keep them free of scratch spills -- a spill
+                    // reload waits for every copy in flight, as they share the
+                    // vector memory counter)
+                    constexpr int FB = RT >= 14 ? 4 : HALF;
 #pragma unroll
-                    for (int ii = 0; ii < HALF; ++ii) {
-                        const f32x4 *fr = xs + (ii * 4) * 64 + lane;
-                        xoh[ii] = __builtin_bit_cast(bf16x8, fr[0]);
-                        xol[ii] = __builtin_bit_cast(bf16x8, fr[64]);
-                        xeh[ii] = __builtin_bit_cast(bf16x8, fr[128]);
-                        xel[ii] = __builtin_bit_cast(bf16x8, fr[192]);
-                    }
+                    for (int i0 = 0; i0 < HALF; i0 += FB) {
+                        bf16x8 xoh[FB], xol[FB], xeh[FB], xel[FB];
 #pragma unroll
-                    for (int ii = 0; ii < HALF; ++ii) {
-                        aS[h * HALF + ii] = mfma_bf16(xoh[ii], boh, aS[h * HALF + ii]);
-                        aA[h * HALF + ii] = mfma_bf16(xeh[ii], beh, aA[h * HALF + ii]);
-                    }
+                        for (int ii = 0; ii < FB; ++ii) {
+                            const f32x4 *fr = xs + ((i0 + ii) * 4) * 64 + lane;
+                            xoh[ii] = __builtin_bit_cast(bf16x8, fr[0]);
+                            xol[ii] = __builtin_bit_cast(bf16x8, fr[64]);
+                            xeh[ii] = __builtin_bit_cast(bf16x8, fr[128]);
+                            xel[ii] = __builtin_bit_cast(bf16x8, fr[192]);
+                        }
+                        const int I0 = h * HALF + i0;
 #pragma unroll
-                    for (int ii = 0; ii < HALF; ++ii) {
-                        aS[h * HALF + ii] = mfma_bf16(xoh[ii], bol, aS[h * HALF + ii]);
-                        aA[h * HALF + ii] = mfma_bf16(xeh[ii], bel, aA[h * HALF + ii]);
-                    }
+                        for (int ii = 0; ii < FB; ++ii) {
+                            aS[I0 + ii] = mfma_bf16(xoh[ii], boh, aS[I0 + ii]);
+                            aA[I0 + ii] = mfma_bf16(xeh[ii], beh, aA[I0 + ii]);
+                        }
 #pragma unroll
-                    for (int ii = 0; ii < HALF; ++ii) {
-                        aS[h * HALF + ii] = mfma_bf16(xol[ii], boh, aS[h * HALF + ii]);
-                        aA[h * HALF + ii] = mfma_bf16(xel[ii], beh, aA[h * HALF + ii]);
+                        for (int ii = 0; ii < FB; ++ii) {
+                            aS[I0 + ii] = mfma_bf16(xoh[ii], bol, aS[I0 + ii]);
+                            aA[I0 + ii] = mfma_bf16(xeh[ii], bel, aA[I0 + ii]);
+                        }
+#pragma unroll
+                        for (int ii = 0; ii < FB; ++ii) {
+                            aS[I0 + ii] = mfma_bf16(xol[ii], boh, aS[I0 + ii]);
+                            aA[I0 + ii] = mfma_bf16(xel[ii], beh, aA[I0 + ii]);
+                        }
                     }
                 } else {
 #pragma unroll
@@ -413,12 +447,14 @@ __device__ __forceinline__ void fused_tiles(const BucketArgs &a, const LaunchArg
                 }
                 finish(t, s);
             }
-            // ---- bond forces (and their BF16 split for the coupling product)
+            // ---- bond forces (and their BF16 split for the coupling product,
+            // slab by slab, so the FP32 forces and the accumulators die early)
 #pragma unroll
-            for (int I = 0; I < RT; ++I) bond_forces(aS[I], aA[I], alpha, a.lin, Gp[I], Gm[I]);
-            if constexpr (BF16) {
-#pragma unroll
-                for (int q = 0; q < KS; ++q) {
+            for (int q = 0; q < KS; ++q) {
+                bond_forces(aS[2 * q], aA[2 * q], alpha, a.lin, Gp[2 * q], Gm[2 * q]);
+                bond_forces(aS[2 * q + 1], aA[2 * q + 1], alpha, a.lin, Gp[2 * q + 1],
+                            Gm[2 * q + 1]);
+                if constexpr (BF16) {
                     split_bf16(Gp[2 * q], Gp[2 * q + 1], gph[q], gpl[q]);
                     split_bf16(Gm[2 * q], Gm[2 * q + 1], gmh[q], gml[q]);
                 }
