@@ -447,16 +447,31 @@ __device__ __forceinline__ void fused_tiles(const BucketArgs &a, const LaunchArg
                 }
                 finish(t, s);
             }
-            // ---- bond forces (and their BF16 split for the coupling product,
-            // slab by slab, so the FP32 forces and the accumulators die early)
+            // ---- bond forces (and their BF16 split for the coupling product;
+            // the longest shapes go slab by slab, so the FP32 forces and the
+            // accumulators die early, the others keep the order that
+            // schedules best for them: all forces, then all splits)
+            if constexpr (RT >= 14) {
 #pragma unroll
-            for (int q = 0; q < KS; ++q) {
-                bond_forces(aS[2 * q], aA[2 * q], alpha, a.lin, Gp[2 * q], Gm[2 * q]);
-                bond_forces(aS[2 * q + 1], aA[2 * q + 1], alpha, a.lin, Gp[2 * q + 1],
-                            Gm[2 * q + 1]);
+                for (int q = 0; q < KS; ++q) {
+                    bond_forces(aS[2 * q], aA[2 * q], alpha, a.lin, Gp[2 * q], Gm[2 * q]);
+                    bond_forces(aS[2 * q + 1], aA[2 * q + 1], alpha, a.lin, Gp[2 * q + 1],
+                                Gm[2 * q + 1]);
+                    if constexpr (BF16) {
+                        split_bf16(Gp[2 * q], Gp[2 * q + 1], gph[q], gpl[q]);
+                        split_bf16(Gm[2 * q], Gm[2 * q + 1], gmh[q], gml[q]);
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int I = 0; I < RT; ++I)
+                    bond_forces(aS[I], aA[I], alpha, a.lin, Gp[I], Gm[I]);
                 if constexpr (BF16) {
-                    split_bf16(Gp[2 * q], Gp[2 * q + 1], gph[q], gpl[q]);
-                    split_bf16(Gm[2 * q], Gm[2 * q + 1], gmh[q], gml[q]);
+#pragma unroll
+                    for (int q = 0; q < KS; ++q) {
+                        split_bf16(Gp[2 * q], Gp[2 * q + 1], gph[q], gpl[q]);
+                        split_bf16(Gm[2 * q], Gm[2 * q + 1], gmh[q], gml[q]);
+                    }
                 }
             }
         }
