@@ -230,9 +230,10 @@ int dm_step_euler(dm_ctx *ctx, int64_t n_steps, double dtau);
    tol > 0 it stops after the first cycle that changes no component of any
    u'_n by more than tol (tol = 0: exactly iters cycles; 8 cycles hold the
    bonds at unit length to ~1e-12 per step at dt_bar = 1e-3).  FP64: one
-   wavefront per chain with the chain in LDS up to M = 341 (tensions by
-   cyclic reduction), one thread per chain beyond (Thomas sweep, global
-   scratch allocated on first use); noise tag 3 (index = bead).
+   wavefront per chain with the chain in registers up to M = 64 and in LDS
+   up to M = 341 (tensions by cyclic reduction), one thread per chain beyond
+   (Thomas sweep, global scratch allocated on first use); noise tag 3
+   (index = bead).
    The state is converted from and back to mode amplitudes once per call.
    Without metric pseudo-forces the scheme samples the constrained ensemble
    exp(-H/T_bar) sqrt(det G), G the constraint metric.  Errors: DM_EINVAL

@@ -68,7 +68,8 @@ hipError_t launch_euler_f64(double *pos, const int32_t *ids, int M, int nch,
 
 // n_steps of the inextensible limit (Eqs. y2-y14) on positions pos (SoA,
 // nch chains of M beads with unit bonds): one wavefront per chain with the
-// chain in LDS up to M = 341, else one thread per chain with its state in
+// chain in registers up to M = 64 and in LDS up to M = 341, else one thread
+// per chain with its state in
 // scr, which holds wlc_scratch_doubles(M, nch) doubles (0 when the chain fits
 // the LDS; scr may then be null).  The tension cycle runs at most iters
 // times and, with tol > 0, stops after a cycle that moves no bond component

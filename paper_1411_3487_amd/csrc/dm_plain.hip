@@ -795,6 +795,170 @@ __global__ __launch_bounds__(64) void wlc_wave_kernel(double *__restrict__ pos,
     }
 }
 
+// Chains of up to 64 beads: one wavefront per chain with bond n and bead n
+// in lane n and the whole chain in registers -- neighbours by cross-lane
+// reads (executed by every lane, then masked), the tension system by the
+// same cyclic reduction with identity rows in the lanes that hold no bond.
+// The noise blocks are drawn one per lane and handed to the beads that use
+// them.  Four chains per workgroup, one per wavefront, no LDS and no
+// barrier; the positions are rebuilt at the end in the serial order of the
+// other kernels.
+constexpr int kWlcRegMaxM = 64;
+
+__device__ __forceinline__ double lane_read(double v, int src)
+{
+    return __shfl(v, src < 0 ? 0 : (src > 63 ? 63 : src), 64);
+}
+
+__global__ __launch_bounds__(256) void wlc_reg_kernel(double *__restrict__ pos,
+                                                      const int32_t *__restrict__ ids, int M,
+                                                      int nch, double T_bar, double dt, int iters,
+                                                      double tol, uint64_t seed, int64_t step0,
+                                                      int n_steps)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int c = blockIdx.x * 4 + wv;
+    if (c >= nch) return;  // a whole wavefront
+    const int N = M - 1, nq = N / 4 + 1;
+    const bool bond = lane >= 1 && lane <= N;  // this lane's bond n = lane exists
+    const bool bead = lane <= N;
+    double *x = pos + (size_t)c * 3 * M;
+    const uint32_t chain = (uint32_t)ids[c];
+    const double amp = sqrt(2.0 * T_bar * dt);
+    double U[3] = {0.0, 0.0, 0.0};
+    if (bond) {  // bonds, scaled to unit length
+        double u[3], s2 = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            u[a] = x[a * M + lane] - x[a * M + lane - 1];
+            s2 += u[a] * u[a];
+        }
+        const double inv = s2 > 0.0 ? 1.0 / sqrt(s2) : 0.0;
+        for (int a = 0; a < 3; ++a) U[a] = u[a] * inv;
+    }
+    double r0[3] = {x[0], x[M], x[2 * M]};  // used in lane 0
+    for (int s = 0; s < n_steps; ++s) {
+        const int64_t k = step0 + s;
+        // noise: lane a nq + q draws block q of component a; bead n takes
+        // element n % 4 of block n / 4
+        double zb[4] = {0.0, 0.0, 0.0, 0.0};
+        if (lane < 3 * nq) {
+            const int a = lane / nq, q = lane - a * nq;
+            normals4_f64(noise_bits(seed, (uint32_t)q, chain, k, (uint32_t)a, kTagWLC), zb);
+        }
+        double NZ[3];
+        for (int a = 0; a < 3; ++a) {
+            const int src = a * nq + (lane >> 2);
+            const double z0 = lane_read(zb[0], src), z1 = lane_read(zb[1], src),
+                         z2 = lane_read(zb[2], src), z3 = lane_read(zb[3], src);
+            const int e = lane & 3;
+            const double z = e == 0 ? z0 : (e == 1 ? z1 : (e == 2 ? z2 : z3));
+            NZ[a] = bead ? amp * z : 0.0;
+        }
+        double UN[3] = {U[0], U[1], U[2]};
+        double D[3], UM[3], UMl[3], UMr[3], F = 0.0;
+        for (int it = 0; it < iters; ++it) {
+            double w[3];
+            {  // midpoint bonds
+                double s2 = 0.0;
+                for (int a = 0; a < 3; ++a) {
+                    w[a] = U[a] + UN[a];
+                    s2 += w[a] * w[a];
+                }
+                const double inv = bond ? 1.0 / sqrt(s2) : 0.0;
+                for (int a = 0; a < 3; ++a) UM[a] = bond ? w[a] * inv : 0.0;
+            }
+            double Dl[3];
+            for (int a = 0; a < 3; ++a) {  // bending gradients and bead displacements
+                UMl[a] = lane_read(UM[a], lane - 1);
+                UMr[a] = lane_read(UM[a], lane + 1);
+                if (lane == 0) UMl[a] = 0.0;
+                if (lane == 63) UMr[a] = 0.0;
+                const double h = bond ? -(UMl[a] + UMr[a]) : 0.0;
+                const double h1 = lane_read(h, lane + 1);
+                const double hn1 = lane + 1 <= N ? h1 : 0.0;
+                D[a] = bead ? (hn1 - h) * dt + NZ[a] : 0.0;
+                const double dprev = lane_read(D[a], lane - 1);
+                Dl[a] = lane >= 1 ? dprev : 0.0;
+            }
+            // row n - 1 of the tension system in lane n; identity elsewhere
+            double ra = 0.0, rb = 1.0, rc = 0.0, rr = 0.0;
+            if (bond) {
+                double wl = 0.0, wm = 0.0, wr = 0.0, wd = 0.0;
+                for (int a = 0; a < 3; ++a) {
+                    wl += w[a] * UMl[a];
+                    wm += w[a] * UM[a];
+                    wr += w[a] * UMr[a];
+                    wd += w[a] * (D[a] - Dl[a]);
+                }
+                ra = wl * dt;
+                rb = -2.0 * wm * dt;
+                rc = wr * dt;
+                rr = -wd;
+            }
+            for (int sd = 1; sd < N; sd *= 2) {
+                const bool hasl = lane - sd >= 1, hasr = lane + sd <= N;
+                const double la = lane_read(ra, lane - sd), lb = lane_read(rb, lane - sd),
+                             lc = lane_read(rc, lane - sd), lr = lane_read(rr, lane - sd);
+                const double qa = lane_read(ra, lane + sd), qb = lane_read(rb, lane + sd),
+                             qc = lane_read(rc, lane + sd), qr = lane_read(rr, lane + sd);
+                double an = 0.0, cn = 0.0, bn = rb, dn = rr;
+                if (hasl) {
+                    const double al = -ra / lb;
+                    an = al * la;
+                    bn += al * lc;
+                    dn += al * lr;
+                }
+                if (hasr) {
+                    const double ga = -rc / qb;
+                    cn = ga * qc;
+                    bn += ga * qa;
+                    dn += ga * qr;
+                }
+                if (bond) {
+                    ra = an;
+                    rb = bn;
+                    rc = cn;
+                    rr = dn;
+                }
+            }
+            F = bond ? rr / rb : 0.0;
+            const double fl = lane_read(F, lane - 1), fr = lane_read(F, lane + 1);
+            double change = 0.0;
+            if (bond) {  // bond update
+                for (int a = 0; a < 3; ++a) {
+                    const double v = U[a] + (D[a] - Dl[a]) +
+                                     ((lane >= 2 ? fl : 0.0) * UMl[a] - 2.0 * F * UM[a] +
+                                      (lane + 1 <= N ? fr : 0.0) * UMr[a]) * dt;
+                    change = fmax(change, fabs(v - UN[a]));
+                    UN[a] = v;
+                }
+            }
+            if (tol > 0.0) {  // the same maximum in every lane: a uniform exit
+                for (int o = 32; o >= 1; o >>= 1) change = fmax(change, __shfl_xor(change, o));
+                if (change <= tol) break;
+            }
+        }
+        {  // bead 0 moves with its own tension, bending and noise
+            const double F1 = lane_read(F, 1);
+            for (int a = 0; a < 3; ++a) {
+                const double um1 = lane_read(UM[a], 1);
+                if (lane == 0) r0[a] += D[a] + F1 * um1 * dt;
+            }
+        }
+        for (int a = 0; a < 3; ++a) U[a] = UN[a];
+    }
+    // positions: every lane forms the same serial sums, lane 0 stores them
+    double v[3];
+    for (int a = 0; a < 3; ++a) v[a] = __shfl(r0[a], 0, 64);
+    if (lane == 0)
+        for (int a = 0; a < 3; ++a) x[a * M] = v[a];
+    for (int n = 1; n <= N; ++n)
+        for (int a = 0; a < 3; ++a) {
+            v[a] += __shfl(U[a], n, 64);
+            if (lane == 0) x[a * M + n] = v[a];
+        }
+}
+
 __global__ void reduce_chains_kernel(const double *__restrict__ acc, double *__restrict__ out,
                                      int width, int nch)
 {
@@ -890,6 +1054,11 @@ hipError_t launch_wlc(double *pos, double *scr, const int32_t *ids, int M, int n
 {
     if (nch == 0 || n_steps == 0) return hipSuccess;
     if (M < 2 || iters < 1) return hipErrorInvalidValue;
+    if (M <= kWlcRegMaxM) {
+        hipLaunchKernelGGL(wlc_reg_kernel, dim3((nch + 3) / 4), dim3(256), 0, st, pos, ids, M, nch,
+                           T_bar, dt, iters, tol, seed, step0, n_steps);
+        return hipGetLastError();
+    }
     const size_t lds = sizeof(double) * wlc_lds_doubles(M);
     if (lds <= kWlcMaxLds) {
         hipLaunchKernelGGL(wlc_wave_kernel, dim3(nch), dim3(64), lds, st, pos, ids, M, T_bar, dt,

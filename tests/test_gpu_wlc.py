@@ -22,11 +22,13 @@ def _device():
     torch.cuda.synchronize()
 
 
-@pytest.mark.parametrize("M", [2, 3, 17, 65, 66, 100, 341, 342])
+@pytest.mark.parametrize("M", [2, 3, 17, 64, 65, 66, 100, 341, 342])
 def test_wlc_matches_oracle(M):
-    """Up to M = 341 one wavefront per chain (bonds over the lanes, several per
-    lane from M = 66, tensions by cyclic reduction); from M = 342 the chain
-    no longer fits the LDS and one thread per chain runs the Thomas sweep."""
+    """Up to M = 64 one wavefront per chain with the chain in registers (bond
+    n in lane n); up to M = 341 one wavefront per chain with the chain in LDS
+    (several bonds per lane from M = 66); both solve for the tensions by
+    cyclic reduction.  From M = 342 one thread per chain runs the Thomas
+    sweep."""
     B, T, dt, n = 7, 0.2, 2e-3, 150
     pos = unit_chains(B, M, M)
     with Context(pos, seed=12, precision="fp64") as ctx:
@@ -38,7 +40,7 @@ def test_wlc_matches_oracle(M):
     assert err < 1e-10
 
 
-@pytest.mark.parametrize("M", [64, 342])
+@pytest.mark.parametrize("M", [64, 100, 342])
 def test_wlc_converged_cycles_match_oracle(M):
     """The cycle stopped at convergence (tol 1e-12, at most 16 passes) on both
     sides: a pass count that differs near the threshold moves a bond by at
