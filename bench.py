@@ -107,10 +107,22 @@ def cpu_baseline(args, pos, nu, ts):
                       chain_ids=np.arange(sub.shape[0]))
     dt = time.perf_counter() - t0
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    # one core: the figure to set beside the paper's single-chain desktop runs
+    one = sub[:32]
+    R1 = oracle.modes_from_positions(one)
+    oracle.set_threads(1)
+    try:
+        t1 = time.perf_counter()
+        oracle.step_modes(R1, nu, ts, args.dtau, 50, seed=1, chain_ids=np.arange(32))
+        dt1 = time.perf_counter() - t1
+    finally:
+        oracle.set_threads(cores)
     return {"value": sub.shape[0] * args.cpu_steps / dt, "unit": "chain-steps/s",
             "cores": cores, "kind": "oracle",
             "sample": f"{sub.shape[0]} chains x {args.beads} beads x {args.cpu_steps} mode "
-                      f"steps (FP64 plain C, OpenMP over chains), {dt:.1f} s"}
+                      f"steps (FP64 plain C, OpenMP over chains), {dt:.1f} s",
+            "single_core": {"value": 32 * 50 / dt1, "unit": "chain-steps/s",
+                            "sample": f"32 chains x 50 steps on one thread, {dt1:.1f} s"}}
 
 
 LENGTHS = [64, 96, 128, 192, 256, 384, 512]
@@ -637,8 +649,18 @@ def main():
                      "kernel": f"fused_kernel ({args.precision}), {k_launch} steps per launch",
                      "kernel_ms": kern * 1e3, "flops_per_chain_step": exec_flops},
     }
+    # Table 2 context: simulated time per hour of computing for one chain
+    # (the paper's desktop: 0.56 ms per hour at 256 bp, Delta t = 15.9 ps)
+    per_hour = lambda rate: rate * dt_ps * 3600.0 * 1e-9
+    out["paper_context"] = {"unit": "ms simulated per hour, one chain",
+                            "paper_desktop_table2": {64: 0.23, 128: 0.56, 256: 0.56,
+                                                     512: 0.26}.get(M),
+                            "this_gpu_per_chain": per_hour(chain_steps / B),
+                            "this_gpu_all_chains": per_hour(chain_steps)}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args, pos, NU_DSDNA, T_STAR_DSDNA)
+        out["paper_context"]["oracle_one_core"] = per_hour(
+            out["cpu_baseline"]["single_core"]["value"])
     print(json.dumps(out))
 
 

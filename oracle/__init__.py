@@ -67,6 +67,7 @@ def _load():
         "orc_bead_force": (None, [_i, _d, _p, _p]),
         "orc_step_euler": (None, [_i, _i, _p, _p, _d, _d, _d, _d, _u64, _i64, _i64]),
         "orc_energy": (_d, [_i, _d, _p]),
+        "orc_set_threads": (None, [_i]),
         "orc_mc_sweeps": (None, [_i, _i, _p, _p, _d, _d, _d, _u64, _i64, _i64, _p]),
         "orc_step_wlc": (None, [_i, _i, _p, _p, _d, _d, _i, _d, _u64, _i64, _i64]),
         "orc_chain_observables": (None, [_i, _p, _p]),
@@ -106,6 +107,11 @@ def gauss4(seed, block, chain, step, comp, tag) -> np.ndarray:
 
 def normal(seed, index, chain, step, comp, tag) -> float:
     return _load().orc_normal(seed, index, chain, step, comp, tag)
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's OpenMP loops over chains (timing only)."""
+    _load().orc_set_threads(int(n))
 
 
 def reduced_params(lam, kappa, kT, a, xi) -> dict:

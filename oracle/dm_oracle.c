@@ -46,6 +46,21 @@
 
 #include "dm_oracle.h"
 
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Threads of the OpenMP loops over chains (timing only: results do not
+   depend on it, every chain is computed the same way by one thread). */
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------------ */
 /* Philox4x32-10 (Salmon et al. 2011): ten rounds of a multiply-xor         */
 /* bijection on a 128-bit counter, with a Weyl-sequence key schedule.       */

@@ -32,6 +32,7 @@ void orc_step_euler(int M, int n_chains, const uint32_t *chain_id, double *pos,
                     double nu, double T_star, double dtau, double gamma_dot,
                     uint64_t seed, int64_t step0, int64_t n_steps);
 double orc_energy(int M, double nu, const double *pos);
+void orc_set_threads(int n);
 void orc_step_wlc(int M, int n_chains, const uint32_t *chain_id, double *pos,
                   double T_bar, double dt, int iters, double tol, uint64_t seed,
                   int64_t step0, int64_t n_steps);
