@@ -308,6 +308,13 @@ const char *dm_tuning_report(const dm_ctx *ctx);
    context.  Errors: DM_EINVAL for r <= 0, y <= 0, k < 1 or NULL outputs. */
 int dm_coarse_grain(double r, double y, int32_t k, double *T_star_k, double *nu_k);
 
+/* Time unit of that coarse-grained chain (Sec. 7b, Eq. g2 with a_k = k a and
+   the friction of k basepairs, xi_k = k xi): real time t = c_k tau_k with
+       c_k = k^3 T*_k (1 - 2 nu_k)^2   [in units of a^2 xi / kT],
+   a the basepair spacing and xi the friction per basepair.  Host only.
+   Errors: as dm_coarse_grain. */
+int dm_coarse_grain_time(double r, double y, int32_t k, double *c_k);
+
 /* Synchronise the context's stream. */
 int dm_sync(dm_ctx *ctx);
 

@@ -66,7 +66,7 @@ EXPORTS = ["dm_init_chains", "dm_set_params", "dm_step_modes", "dm_step_euler", 
            "dm_step_wlc",
            "dm_observables", "dm_observables_size", "dm_get_positions", "dm_get_modes",
            "dm_save_state", "dm_load_state", "dm_get_step", "dm_get_tiling",
-           "dm_tuning_report", "dm_coarse_grain", "dm_sync", "dm_destroy", "dm_last_error"]
+           "dm_tuning_report", "dm_coarse_grain", "dm_coarse_grain_time", "dm_sync", "dm_destroy", "dm_last_error"]
 
 _lib = None
 
@@ -99,6 +99,8 @@ def load(path: str = LIB_PATH):
         "dm_get_step": ([vp, ctypes.POINTER(i64)], ctypes.c_int),
         "dm_get_tiling": ([vp, vp, sz, ctypes.POINTER(i32)], ctypes.c_int),
         "dm_tuning_report": ([vp], ctypes.c_char_p),
+        "dm_coarse_grain_time": ([ctypes.c_double, ctypes.c_double, i32,
+                                  ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
         "dm_coarse_grain": ([ctypes.c_double, ctypes.c_double, i32, ctypes.POINTER(ctypes.c_double),
                              ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
         "dm_sync": ([vp], ctypes.c_int),
@@ -121,6 +123,16 @@ def coarse_grain(r: float, y: float, k: int):
     if rc != DM_OK:
         raise DMError(rc, lib.dm_last_error(None).decode())
     return t.value, n.value
+
+
+def coarse_grain_time(r: float, y: float, k: int) -> float:
+    """Time unit c_k of that chain in units of a^2 xi / kT (dm_coarse_grain_time)."""
+    lib = load()
+    c = ctypes.c_double()
+    rc = lib.dm_coarse_grain_time(r, y, k, ctypes.byref(c))
+    if rc != DM_OK:
+        raise DMError(rc, lib.dm_last_error(None).decode())
+    return c.value
 
 
 class Context:

@@ -1086,6 +1086,17 @@ int dm_coarse_grain(double r, double y, int32_t k, double *T_star_k, double *nu_
     return DM_OK;
 }
 
+int dm_coarse_grain_time(double r, double y, int32_t k, double *c_k)
+{
+    double T = 0.0, nu = 0.0;
+    if (!c_k) return fail(nullptr, DM_EINVAL, "coarse graining needs an output");
+    const int rc = dm_coarse_grain(r, y, k, &T, &nu);
+    if (rc) return rc;
+    const double kk = (double)k, s = 1.0 - 2.0 * nu;
+    *c_k = kk * kk * kk * T * s * s;
+    return DM_OK;
+}
+
 const char *dm_last_error(const dm_ctx *ctx)
 {
     return ctx ? ctx->err.c_str() : g_init_error.c_str();

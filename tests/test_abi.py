@@ -81,3 +81,39 @@ def test_coarse_grain_reproduces_table3():
     assert nu3 == pytest.approx(120.0 ** 2 / (2 * 120.0 ** 2 + 9 * 12000.0), rel=1e-14)
     with pytest.raises(_lib.DMError):
         _lib.coarse_grain(-1.0, 1.0, 1)
+
+
+def test_coarse_grain_time_unit_reproduces_table5():
+    """Sec. 7b, Table 5: t = c_k tau under coarse-graining by k.  The ratios
+    c_k / c_1 follow from Table 3's parameters with a_k = k a and xi_k = k xi
+    (Eq. g2) to the printed digits.  The absolute scale: c_1 = 1.54 ps in the
+    table is 10x the unit behind Table 2 (c_1 = T*/b^2 a^2 xi/kT = 0.153 ps
+    with a^2 xi/kT = 52.0 ps, so that dtau = 10, 50, 100 give its 1.59, 7.96,
+    15.9 ps), the same factor as the prose time unit of Sec. 7b."""
+    rows = np.loadtxt(os.path.join(ROOT, "tests", "golden", "table5_time_units.txt"))
+    c1 = _lib.coarse_grain_time(120.0, 12000.0, 1)
+    for k, ck in rows:
+        c = _lib.coarse_grain_time(120.0, 12000.0, int(k))
+        assert c / c1 == pytest.approx(ck / rows[0, 1], rel=2e-5), k
+    assert c1 * 52.0 == pytest.approx(0.153, rel=2e-3)
+    assert rows[0, 1] / (c1 * 52.0) == pytest.approx(10.0, rel=0.01)
+    with pytest.raises(_lib.DMError):
+        _lib.coarse_grain_time(120.0, 12000.0, 0)
+
+
+def test_coarse_grain_reproduces_factin_table4():
+    """Appendix A, Table 4 (f-actin, r = 1591, y = 7.65e7, a^2 xi/kT = 0.4 us):
+    in bending units (tau-bar = nu tau) the temperature is T*_k / nu_k and
+    the time unit c_k / nu_k; both columns follow to the printed digits.  The
+    printed nu_k column sits 1.4-1.5 % below r^2 / (2 r^2 + k^2 y) at every
+    k: it matches r = 1579 instead (a slightly different monomer length),
+    while the other two columns need r = 1591."""
+    rows = np.loadtxt(os.path.join(ROOT, "tests", "golden", "table4_factin.txt"))
+    for k, tbar, nu_t, cbar in rows:
+        t, nu = _lib.coarse_grain(1591.0, 7.65e7, int(k))
+        c = _lib.coarse_grain_time(1591.0, 7.65e7, int(k))
+        assert t / nu == pytest.approx(tbar, rel=3e-3), k
+        assert 0.4 * c / nu == pytest.approx(cbar, rel=6e-3), k
+        assert 1.010 < nu / nu_t < 1.016, k
+        t2, nu2 = _lib.coarse_grain(1579.2, 7.65e7, int(k))
+        assert nu2 == pytest.approx(nu_t, rel=1e-3), k
