@@ -181,3 +181,33 @@ def test_fused_observables_match_fp64_of_the_same_state(prec, M):
         assert err < 2e-6, (name, err)
     want_m2 = (R64 ** 2).sum(axis=1)
     assert np.allclose(m2, want_m2, rtol=2e-6, atol=1e-12 * want_m2.max())
+
+
+def test_benchmark_launch_configuration_at_full_size():
+    """4096 x 256 bp, split BF16, in the launch configuration the benchmark
+    times: autotuned tile shapes, sampling blocks of 100 steps replayed as
+    graphs with the observables of each block taken beside the next launch.
+    After 300 steps, sampled chains are recomputed by the oracle one by one:
+    positions, and the per-chain observables of the final state, which the
+    last (eager) observation wrote."""
+    B, M, n = 4096, 256, 300
+    pos = inputs.straight_chains(B, M, B_FAC, seed=1, random_orientation=True)
+    with Context(pos, seed=1, precision="bf16x3") as ctx:
+        ctx.set_params([M], [100.0], T_star=TS, nu=NU, sample_every=100, use_graphs=True,
+                       autotune=True)
+        ctx.step_modes(n)
+        got = ctx.positions()
+        obs = ctx.chain_observables()
+        acc = ctx.accumulators()[0]
+    assert acc["n_samples"] == 3 and acc["n_chains"] == B
+    for c in [0, 4, 5, 1027, 2048, 4095]:
+        R = oracle.step_modes(oracle.modes_from_positions(pos[c][None]), NU, TS, 100.0, n,
+                              seed=1, chain_ids=[c])
+        want = oracle.positions_from_modes(R)
+        err = rel_pos_err(got[c][None], want)
+        print(f"chain {c}: 300-step rel err {err:.2e}")
+        assert err < 1e-4, (c, err)
+        o = oracle.chain_observables(want)[0]
+        L = (M - 1) * B_FAC
+        assert abs(obs[c, 1] - o[1]) < 1e-3 * L * L, c       # L^2
+        assert abs(obs[c, 0] - o[0]) < 1e-4 * B_FAC, c       # mean bond length
