@@ -43,8 +43,11 @@ def oracle_positions(pos0, dtau, n, seed, ids=None, step0=0, gamma_dot=0.0, nonl
 # ----------------------------------------------------------------- FP64 path
 @pytest.mark.parametrize("B,M,dtau,n", [(1, 64, 10.0, 1000), (7, 100, 10.0, 300),
                                         (3, 255, 100.0, 100), (2, 2, 0.5, 200),
-                                        (4, 3, 0.2, 200), (5, 17, 1.0, 300)])
+                                        (4, 3, 0.2, 200), (5, 17, 1.0, 300),
+                                        (2, 2047, 100.0, 10), (2, 2048, 100.0, 10)])
 def test_fp64_mode_steps_match_oracle(B, M, dtau, n):
+    """Lengths from the smallest (2 beads) to the largest the FP64 path takes
+    (2048), with and without the multiple-of-16 GEMM pipeline."""
     pos = inputs.straight_chains(B, M, B_FAC, seed=M, random_orientation=True)
     with Context(pos, seed=11, precision="fp64") as ctx:
         ctx.set_params([M], [dtau], T_star=TS, nu=NU)
@@ -94,9 +97,9 @@ def test_fp64_free_modes_match_oracle():
     assert rel_pos_err(got, ref) < FP64_TOL
 
 
-@pytest.mark.parametrize("M", [2, 5, 64, 130])
+@pytest.mark.parametrize("M", [2, 5, 64, 130, 2048])
 def test_euler_matches_oracle(M):
-    B, dtau, n = 5, 0.1, 500
+    B, dtau, n = 5, 0.1, (500 if M < 1000 else 50)
     pos = inputs.straight_chains(B, M, B_FAC, seed=20 + M)
     with Context(pos, seed=7, precision="fp64") as ctx:
         ctx.set_params([M], [10.0], T_star=TS, nu=NU, gamma_dot=1e-3)
