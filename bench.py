@@ -27,7 +27,7 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--workload", default="modes",
-                    choices=["modes", "uneven", "shear", "mc", "dtmax", "dtmax_t", "wlc"],
+                    choices=["modes", "uneven", "shear", "mc", "dtmax", "dtmax_t", "wlc", "euler"],
                     help="modes: 4096 x 256 bp (the headline line); uneven: 8192 chains of "
                          "64..512 bp in one launch; shear: 2048 x 256 bp under simple shear "
                          "at Wi = 1, 10, 100 (tumbling and extension, FP32 vs FP64); mc: "
@@ -268,13 +268,84 @@ def mc_workload(args):
     t0 = time.perf_counter()
     acc = ctx.step_mc(sweeps)
     wall = time.perf_counter() - t0
+    R0 = ctx.modes()
     ctx.close()
     props = B * sweeps * 3 * (M - 1)
-    print(json.dumps({"metric": "Metropolis proposals/s (mode representation, FP64)",
-                      "value": props / wall, "unit": "proposals/s",
-                      "chain_sweeps_per_s": B * sweeps / wall, "acceptance": acc / props,
-                      "config": {"workload": f"{B} chains x {M} bp, {sweeps} sweeps, "
-                                             "step_scale 3"}}))
+    flops = MC_FLOPS_PER_BOND * (M - 1)          # per proposal
+    out = {"metric": "Metropolis proposals/s (mode representation, FP64)",
+           "value": props / wall, "unit": "proposals/s",
+           "chain_sweeps_per_s": B * sweeps / wall, "acceptance": acc / props,
+           "config": {"workload": f"{B} chains x {M} bp, {sweeps} sweeps, step_scale 3"},
+           "roofline": {"bound": "alu", "achieved": props / wall * flops / 1e12, "peak": 78.6,
+                        "unit": "TFLOP/s", "frac": props / wall * flops / 78.6e12,
+                        "flops_per_proposal": flops}}
+    if not args.no_cpu_baseline:
+        import numpy as np
+        import oracle
+        t0 = time.perf_counter()
+        oracle.mc_sweeps(R0[:256], NU_DSDNA, T_STAR_DSDNA, 3.0, 10, seed=1, step0=22,
+                         chain_ids=np.arange(256))
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": 256 * 10 * 3 * (M - 1) / dt, "unit": "proposals/s",
+                               "cores": int(os.environ.get("OMP_NUM_THREADS",
+                                                           os.cpu_count() or 1)),
+                               "kind": "oracle", "sample": f"256 chains x 10 sweeps, {dt:.1f} s"}
+    print(json.dumps(out))
+
+
+# Floating-point operations of one Metropolis proposal per bond (the change
+# of H' of Eq. b3 when one mode component moves): the new bond length 10,
+# two square roots and the stretching terms 8, the bending cross terms 12.
+MC_FLOPS_PER_BOND = 30
+# Of one Euler step per bead (Eqs. b3-b5): bond vector and length 9, the
+# stretching and bending gradient 21, the bead update with noise and shear
+# 15, and the Box-Muller share of the noise 15.
+EULER_FLOPS_PER_BEAD = 60
+
+
+def euler_workload(args):
+    """The bead-space Euler baseline (Eqs. b3-b5, FP64) on 4096 chains x 256 bp
+    at the paper's safe time step dtau = 0.1: bead-steps/s and simulated time,
+    beside the mode scheme's step of dtau = 100 at the same chain length."""
+    import numpy as np
+    import torch
+    from paper_1411_3487_amd import Context, inputs, NU_DSDNA, T_STAR_DSDNA
+    torch.cuda.set_device(0)
+    b = 1.0 / (1.0 - 2.0 * NU_DSDNA)
+    B, M, dtau, n = args.chains, args.beads, 0.1, 2000
+    pos = inputs.straight_chains(B, M, b, seed=1, random_orientation=True)
+    stream = torch.cuda.current_stream()
+    with Context(pos, seed=1, precision="fp64", stream=stream) as ctx:
+        ctx.set_params([M], [args.dtau], T_star=T_STAR_DSDNA, nu=NU_DSDNA)
+        ctx.step_euler(20, dtau)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        ctx.step_euler(n, dtau)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        sec = e0.elapsed_time(e1) * 1e-3
+        x = ctx.positions()
+    rate = B * M * n / sec
+    out = {"metric": "bead-steps/s, bead-space Euler (FP64)", "value": rate,
+           "unit": "bead-steps/s", "chain_steps_per_s": B * n / sec,
+           "simulated_ns_per_s_per_chain": n / sec * dtau * 0.159119 * 1e-3,
+           "state_finite": bool(np.all(np.isfinite(x))),
+           "config": {"workload": f"{B} chains x {M} bp, dtau 0.1, {n} steps in one launch"},
+           "roofline": {"bound": "alu", "achieved": rate * EULER_FLOPS_PER_BEAD / 1e12,
+                        "peak": 78.6, "unit": "TFLOP/s",
+                        "frac": rate * EULER_FLOPS_PER_BEAD / 78.6e12,
+                        "flops_per_bead_step": EULER_FLOPS_PER_BEAD}}
+    if not args.no_cpu_baseline:
+        import oracle
+        t0 = time.perf_counter()
+        oracle.step_euler(pos[:256], NU_DSDNA, T_STAR_DSDNA, dtau, 1000, seed=1)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": 256 * M * 1000 / dt, "unit": "bead-steps/s",
+                               "cores": int(os.environ.get("OMP_NUM_THREADS",
+                                                           os.cpu_count() or 1)),
+                               "kind": "oracle", "sample": f"256 chains x 1000 steps, {dt:.1f} s"}
+    print(json.dumps(out))
 
 
 def dtmax_workload(args):
@@ -548,6 +619,8 @@ def main():
         return dtmax_t_workload(args)
     if args.workload == "mc" and args.gpus == 1:
         return mc_workload(args)
+    if args.workload == "euler" and args.gpus == 1:
+        return euler_workload(args)
     if args.workload == "dtmax" and args.gpus == 1:
         return dtmax_workload(args)
     if args.profile_launches:
