@@ -810,6 +810,22 @@ __device__ __forceinline__ double lane_read(double v, int src)
     return __shfl(v, src < 0 ? 0 : (src > 63 ? 63 : src), 64);
 }
 
+// The value of lane - 1 (lane 0 gets 0) or of lane + 1 (lane 63 gets 0): DPP
+// whole-wavefront shifts, two 32-bit moves per double, no LDS crossbar.
+template <int CTRL>
+__device__ __forceinline__ double wave_shift(double v)
+{
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, 0xF, 0xF,
+                                                              true);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL,
+                                                              0xF, 0xF, true);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+constexpr int kWaveShr1 = 0x138, kWaveShl1 = 0x130;
+__device__ __forceinline__ double from_prev(double v) { return wave_shift<kWaveShr1>(v); }
+__device__ __forceinline__ double from_next(double v) { return wave_shift<kWaveShl1>(v); }
+
 __global__ __launch_bounds__(256) void wlc_reg_kernel(double *__restrict__ pos,
                                                       const int32_t *__restrict__ ids, int M,
                                                       int nch, double T_bar, double dt, int iters,
@@ -869,15 +885,15 @@ __global__ __launch_bounds__(256) void wlc_reg_kernel(double *__restrict__ pos,
             }
             double Dl[3];
             for (int a = 0; a < 3; ++a) {  // bending gradients and bead displacements
-                UMl[a] = lane_read(UM[a], lane - 1);
-                UMr[a] = lane_read(UM[a], lane + 1);
+                UMl[a] = from_prev(UM[a]);
+                UMr[a] = from_next(UM[a]);
                 if (lane == 0) UMl[a] = 0.0;
                 if (lane == 63) UMr[a] = 0.0;
                 const double h = bond ? -(UMl[a] + UMr[a]) : 0.0;
-                const double h1 = lane_read(h, lane + 1);
+                const double h1 = from_next(h);
                 const double hn1 = lane + 1 <= N ? h1 : 0.0;
                 D[a] = bead ? (hn1 - h) * dt + NZ[a] : 0.0;
-                const double dprev = lane_read(D[a], lane - 1);
+                const double dprev = from_prev(D[a]);
                 Dl[a] = lane >= 1 ? dprev : 0.0;
             }
             // row n - 1 of the tension system in lane n; identity elsewhere
@@ -897,10 +913,16 @@ __global__ __launch_bounds__(256) void wlc_reg_kernel(double *__restrict__ pos,
             }
             for (int sd = 1; sd < N; sd *= 2) {
                 const bool hasl = lane - sd >= 1, hasr = lane + sd <= N;
-                const double la = lane_read(ra, lane - sd), lb = lane_read(rb, lane - sd),
-                             lc = lane_read(rc, lane - sd), lr = lane_read(rr, lane - sd);
-                const double qa = lane_read(ra, lane + sd), qb = lane_read(rb, lane + sd),
-                             qc = lane_read(rc, lane + sd), qr = lane_read(rr, lane + sd);
+                double la, lb, lc, lr, qa, qb, qc, qr;
+                if (sd == 1) {  // neighbours by DPP shifts
+                    la = from_prev(ra), lb = from_prev(rb), lc = from_prev(rc), lr = from_prev(rr);
+                    qa = from_next(ra), qb = from_next(rb), qc = from_next(rc), qr = from_next(rr);
+                } else {
+                    la = lane_read(ra, lane - sd), lb = lane_read(rb, lane - sd);
+                    lc = lane_read(rc, lane - sd), lr = lane_read(rr, lane - sd);
+                    qa = lane_read(ra, lane + sd), qb = lane_read(rb, lane + sd);
+                    qc = lane_read(rc, lane + sd), qr = lane_read(rr, lane + sd);
+                }
                 double an = 0.0, cn = 0.0, bn = rb, dn = rr;
                 if (hasl) {
                     const double al = -ra / lb;
@@ -922,7 +944,7 @@ __global__ __launch_bounds__(256) void wlc_reg_kernel(double *__restrict__ pos,
                 }
             }
             F = bond ? rr / rb : 0.0;
-            const double fl = lane_read(F, lane - 1), fr = lane_read(F, lane + 1);
+            const double fl = from_prev(F), fr = from_next(F);
             double change = 0.0;
             if (bond) {  // bond update
                 for (int a = 0; a < 3; ++a) {
