@@ -658,7 +658,8 @@ def main():
     ctx.set_params([M], [args.dtau], T_star=T_STAR_DSDNA, nu=NU_DSDNA,
                    sample_every=args.sample_every, use_graphs=not args.no_graphs,
                    autotune=not args.no_autotune)
-    tiling = ctx.tiling()[0]
+    tiling, report = ctx.tiling()[0], ctx.tuning_report()
+    shape = "split" if tiling["split"] else ("resident" if tiling["resident"] else "streamed")
     ctx.step_modes(args.warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -670,8 +671,7 @@ def main():
     # dominant kernel alone, in the launch shape of the timed loop: one fused
     # launch covers the steps between two observable samples
     ctx.set_params([M], [args.dtau], T_star=T_STAR_DSDNA, nu=NU_DSDNA, sample_every=0,
-                   tiles_per_wg=int(tiling["tpw"]),
-                   table_mode="resident" if tiling["resident"] else "streamed")
+                   tiles_per_wg=int(tiling["tpw"]), table_mode=shape)
     k_launch = args.sample_every if args.sample_every > 0 else 100
     kern = sorted(time_steps(ctx, torch, k_launch, stream) for _ in range(9))[4]
     ctx.close()
@@ -709,9 +709,9 @@ def main():
                                f"{args.sample_every} steps",
                    "chains": B, "beads": M, "parallelism": "1 GPU, chains data-parallel",
                    "launch": {"graphs": not args.no_graphs, "autotune": not args.no_autotune,
-                              "tables": "resident" if tiling["resident"] else "streamed",
-                              "tiles_per_wg": int(tiling["tpw"]),
-                              "coupling_row_tiles": int(tiling["JC"]), "row_tiles": int(tiling["RT"])}},
+                              "tables": shape, "tiles_per_wg": int(tiling["tpw"]),
+                              "coupling_row_tiles": int(tiling["JC"]), "row_tiles": int(tiling["RT"]),
+                              "tuning_report": report.strip().splitlines()}},
         "bead_steps_per_s": chain_steps * M,
         "simulated_ns_per_s": chain_steps / B * dt_ps * 1e-3,
         "fp64_plain_chain_steps_per_s": fp64_rate,

@@ -122,7 +122,7 @@ extern "C" {
 #define DM_CORR_COUNT    3
 
 /* dm_get_tiling(): DM_NTILING doubles per length bucket. */
-#define DM_NTILING       8
+#define DM_NTILING       9
 #define DM_TI_M          0  /* beads per chain */
 #define DM_TI_NCHAINS    1
 #define DM_TI_RT         2  /* 16-row tiles per half transform (fused) */
@@ -131,6 +131,8 @@ extern "C" {
 #define DM_TI_TPW        5  /* tiles of 5 chains per workgroup */
 #define DM_TI_ITEMS      6  /* workgroups of this bucket per launch */
 #define DM_TI_ITEM_US    7  /* measured us per workgroup-step (autotune), or 0 */
+#define DM_TI_SPLIT      8  /* 1: one tile per workgroup, its bond rows and
+                               mode tiles divided among 4 wavefronts */
 
 typedef struct dm_ctx dm_ctx;
 
@@ -170,10 +172,19 @@ typedef struct {
                                 chains per workgroup where the tables are
                                 resident (streamed tables always take 4) */
     int32_t table_mode;      /* fused paths: 0 = automatic, 1 = tables
-                                resident in LDS, 2 = streamed from L2, each
-                                where that form exists for the length (it
-                                overrides the autotuner); results do not
-                                depend on the tile shape */
+                                resident in LDS, 2 = streamed from L2,
+                                3 = split tiles (one tile of 5 chains per
+                                workgroup, its bond rows and mode tiles
+                                divided among 4 wavefronts: for launches
+                                with fewer tiles than SIMDs; lengths with
+                                RT = 4, 8, 12, 16, i.e. 65..128, 193..256,
+                                321..384, 449..512 beads), each where that
+                                form exists for the length (it overrides the
+                                autotuner).  Automatic without autotune:
+                                split tiles where they exist when the launch
+                                has no more tiles than compute units, else
+                                resident tables where they fit.  Results do
+                                not depend on the tile shape */
     int32_t corr_lags;       /* 0..14: number of lags of the time
                                 correlations in the accumulators (a ring of
                                 2^(corr_lags-1) past samples per chain is

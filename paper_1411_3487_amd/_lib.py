@@ -38,8 +38,8 @@ CHAIN_OBS_NAMES = ["bond_mean", "L2", "Lx", "Ly", "Lz", "cmx", "cmy", "cmz",
                    "umx", "umy", "umz", "dmx", "dmy", "dmz", "xspan", "bond2_mean"]
 ACC_NAMES = ["M", "n_chains", "n_samples", "bond", "bond2", "L2", "msd_cm", "dmid2", "xspan",
              "tumbles", "tau", "tau2", "n_tau"]
-DM_NTILING = 8
-TILING_NAMES = ["M", "n_chains", "RT", "JC", "resident", "tpw", "items", "item_us"]
+DM_NTILING = 9
+TILING_NAMES = ["M", "n_chains", "RT", "JC", "resident", "tpw", "items", "item_us", "split"]
 
 
 class DMError(RuntimeError):
@@ -209,7 +209,8 @@ class Context:
         p.use_graphs = 1 if use_graphs else 0
         p.tiles_per_wg = tiles_per_wg
         p.corr_lags = corr_lags
-        p.table_mode = {"auto": 0, "resident": 1, "streamed": 2}.get(table_mode, table_mode)
+        p.table_mode = {"auto": 0, "resident": 1, "streamed": 2, "split": 3}.get(table_mode,
+                                                                                 table_mode)
         self._check(self.lib.dm_set_params(self.h, ctypes.byref(p)))
 
     def tiling(self) -> list:

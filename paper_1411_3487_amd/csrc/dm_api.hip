@@ -535,8 +535,8 @@ int dm_set_params(dm_ctx *ctx, const dm_params *p)
     if (p->n_lengths <= 0 || !p->lengths || !p->dt)
         return fail(ctx, DM_EINVAL, "lengths / dt tables are empty");
     if (p->sample_every < 0) return fail(ctx, DM_EINVAL, "sample_every must be >= 0");
-    if (p->tiles_per_wg < 0 || p->tiles_per_wg > 4 || p->table_mode < 0 || p->table_mode > 2)
-        return fail(ctx, DM_EINVAL, "tiles_per_wg must be 0..4 and table_mode 0..2");
+    if (p->tiles_per_wg < 0 || p->tiles_per_wg > 4 || p->table_mode < 0 || p->table_mode > 3)
+        return fail(ctx, DM_EINVAL, "tiles_per_wg must be 0..4 and table_mode 0..3");
     if (p->corr_lags < 0 || p->corr_lags > 14)
         return fail(ctx, DM_EINVAL, "corr_lags must be 0..14");
     std::vector<double> dtau(ctx->buckets.size());
@@ -603,6 +603,13 @@ int dm_set_params(dm_ctx *ctx, const dm_params *p)
             std::vector<dm::FusedBucket *> fb;
             for (Bucket &b : ctx->buckets) fb.push_back(&b.fused);
             DM_HIP(ctx, dm::fused_autotune(fb, ctx->seed, 64, ctx->stream, ctx->tune_report));
+        } else if (!p->table_mode) {
+            // untimed: split tiles when a wavefront per tile would leave
+            // compute units idle
+            size_t tiles = 0;
+            for (const Bucket &b : ctx->buckets) tiles += (size_t)b.fused.ntiles;
+            if (ctx->ncu > 0 && tiles <= (size_t)ctx->ncu)
+                for (Bucket &b : ctx->buckets) dm::fused_force_shape(b.fused, 3, 0);
         }
         if (p->tiles_per_wg || p->table_mode)
             for (Bucket &b : ctx->buckets)
@@ -1069,6 +1076,7 @@ int dm_get_tiling(const dm_ctx *ctx, double *out, size_t len, int32_t *n_buckets
         o[DM_TI_TPW] = fused ? f.tpw : 0;
         o[DM_TI_ITEMS] = fused ? (f.ntiles + f.tpw - 1) / f.tpw : 0;
         o[DM_TI_ITEM_US] = fused ? f.item_us : 0;
+        o[DM_TI_SPLIT] = fused ? f.split : 0;
     }
     return DM_OK;
 }

@@ -25,7 +25,9 @@ struct FusedBucket {
     double *d_R0s = nullptr;
     int JC = 0;              // coupling row tiles with non-negligible C_p
     int resident = 0;        // tables held in LDS for the whole launch
-    int tpw = 4;             // tiles per workgroup (1..4; 4 when streamed)
+    int tpw = 4;             // tiles per workgroup (1..4; 4 when streamed, 1 split)
+    int split = 0;           // 1: one tile per workgroup, its rows and modes
+                             // divided among the 4 wavefronts
     double item_us = 0.0;    // measured time of one workgroup-step (0: model)
     int n = 0;               // chains
     const int32_t *ids = nullptr;  // device: global chain index per local chain
@@ -66,8 +68,9 @@ hipError_t fused_autotune(std::vector<FusedBucket *> &bs, uint64_t seed, int ste
 // Time of one workgroup item of the bucket for one step, in microseconds:
 // measured by the autotuner, else the cost model.
 double fused_item_us(const FusedBucket &f);
-// Force a tile shape where it exists: table_mode 1 resident, 2 streamed (0
-// keeps the current); tpw 1..4 where resident (0 keeps the current).
+// Force a tile shape where it exists: table_mode 1 resident, 2 streamed,
+// 3 split (0 keeps the current); tpw 1..4 where resident (0 keeps the
+// current).
 void fused_force_shape(FusedBucket &f, int table_mode, int tpw);
 // Device step counter of replayed graphs: *d_step = value, *d_step += n.
 hipError_t fused_set_step(int64_t *d_step, int64_t value, hipStream_t st);

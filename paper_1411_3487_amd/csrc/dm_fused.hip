@@ -475,7 +475,10 @@ __device__ __forceinline__ void fused_tiles(const BucketArgs &a, const LaunchArg
                 }
             }
         }
-        // ---- per mode tile J: E R + W eta (+ shear) and the coupling.  Lane
+        // ---- per mode tile J: E R + W eta (+ shear) and the coupling, with
+        // every multiply-add written as an explicit fma, so that the
+        // rounding does not depend on which products the compiler fuses in
+        // each tile shape (all shapes give the same bits).  Lane
         // holds half-mode slots j = 16J + 4g + r: odd p = 2j + 1 in Ro[J][r],
         // even p = 2j + 2 (scaled) in Re[J][r].  Normal p of the step is
         // element p % 4 of Philox block p / 4, so a lane group draws normals
@@ -497,15 +500,15 @@ __device__ __forceinline__ void fused_tiles(const BucketArgs &a, const LaunchArg
                                     (uint32_t)alpha, kTagMode),
                          z + 4);
             const float zn = __shfl(z[0], (lane + 16) & 63, 64);
-            if (J > 0) Re[J - 1][3] += (g == 3) ? wcarry * zn : 0.0f;
+            if (J > 0) Re[J - 1][3] = __builtin_fmaf(g == 3 ? wcarry : 0.0f, zn, Re[J - 1][3]);
             const f32x4 Eo = cf[(kEo * RT + J) * 4 + g], Wo = cf[(kWo * RT + J) * 4 + g];
             const f32x4 Ee = cf[(kEe * RT + J) * 4 + g], We = cf[(kWe * RT + J) * 4 + g];
             f32x4 ao, ae;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const float ze = r < 3 ? z[2 * r + 2] : (g < 3 ? zn : 0.0f);
-                ao[r] = Eo[r] * Ro[J][r] + Wo[r] * z[2 * r + 1];
-                ae[r] = Ee[r] * Re[J][r] + We[r] * ze;
+                ao[r] = __builtin_fmaf(Eo[r], Ro[J][r], Wo[r] * z[2 * r + 1]);
+                ae[r] = __builtin_fmaf(Ee[r], Re[J][r], We[r] * ze);
             }
             wcarry = We[3];
             if (a.gdt != 0.0) {
@@ -515,16 +518,16 @@ __device__ __forceinline__ void fused_tiles(const BucketArgs &a, const LaunchArg
                     // R^y of the same chain, for the x lanes only.  The lane
                     // move runs with every lane active (a DPP read from a lane
                     // masked off by a branch returns 0), then is masked.
-                    ao[r] += Go[r] * (xlane * dpp<kRowShl1>(Ro[J][r]));
-                    ae[r] += Ge[r] * (xlane * dpp<kRowShl1>(Re[J][r]));
+                    ao[r] = __builtin_fmaf(Go[r], xlane * dpp<kRowShl1>(Ro[J][r]), ao[r]);
+                    ae[r] = __builtin_fmaf(Ge[r], xlane * dpp<kRowShl1>(Re[J][r]), ae[r]);
                 }
             }
             if (J == 0) {
                 // centre of mass (p = 0, normal 0 of the g = 0 lanes): free
                 // random walk in FP64, shear drift from R_0^y
                 const double r0y = __shfl(r0, (lane + 1) & 63, 64);
-                double nr0 = r0 + a.W0 * (double)z[0];
-                if (alpha == 0) nr0 += a.gdt * r0y;
+                double nr0 = __builtin_fma(a.W0, (double)z[0], r0);
+                if (alpha == 0) nr0 = __builtin_fma(a.gdt, r0y, nr0);
                 r0 = com_lane ? nr0 : 0.0;
             }
             if (couple) {
@@ -577,7 +580,7 @@ __device__ __forceinline__ void fused_tiles(const BucketArgs &a, const LaunchArg
                 }
                 const f32x4 Ce = cf[(kCe * RT + J) * 4 + g];
 #pragma unroll
-                for (int r = 0; r < 4; ++r) ae[r] += Ce[r] * ce[r];
+                for (int r = 0; r < 4; ++r) ae[r] = __builtin_fmaf(Ce[r], ce[r], ae[r]);
                 finish(t, s);
             }
             Ro[J] = ao;
@@ -591,6 +594,387 @@ __device__ __forceinline__ void fused_tiles(const BucketArgs &a, const LaunchArg
     for (int t = 0; t < RT; ++t) {
         Rw[(0 * RT + t) * 64 + lane] = Ro[t];
         Rw[(1 * RT + t) * 64 + lane] = Re[t];
+    }
+    if (com_lane) a.R0[(size_t)tile * 16 + col] = r0;
+}
+
+// ---- Split tile: one tile of 5 chains per workgroup, its work divided
+// among the 4 wavefronts, for launches with fewer tiles than the GPU has
+// SIMDs (with one wavefront per tile, 1024 chains make 205 wavefronts).
+// Wavefront w owns the mode tiles J = w, w + 4, ... (their amplitudes, noise
+// and update) and the half-bond row tiles I = w, w + 4, ... (their rows of
+// u = chi R and their bond forces); the round-robin spreads the few coupled
+// mode tiles J < jc over the wavefronts.  Each step they exchange through LDS
+// what their products take from the others:
+//   Rb  the amplitudes (split BF16 or FP32), the B operand of u = chi R;
+//   Gb  the bond forces G+ and G- (split or FP32), the B operand of the
+//       coupling product;
+//   cz  normal 0 of lane group 0 of each mode tile, which lane group 3 of the
+//       previous tile takes for its even slot r = 3.
+// Three barriers a step: forces written (B), normals written (C), amplitudes
+// written (A).  Each accumulator sees the same products in the same order as
+// in fused_tiles, and every update the same operations, so the states are
+// bit-identical to the other tile shapes.  The table fragments a wavefront
+// reads (its own bond rows, its own coupling rows) are read by no other
+// wavefront, so they go from L2 straight to registers: up to RT = 12 the
+// u = chi R fragments of the own rows stay in registers for the whole
+// launch, and at RT = 16 a ring keeps DU = 4 K slabs of them in flight (the
+// first ones of the next step issued after the update, when the coupling
+// registers are free); a mode tile's first DC K slabs of coupling rows are
+// loaded before its noise is drawn.
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+
+// s_waitcnt lgkmcnt(0) alone: this wavefront's LDS accesses have completed.
+__device__ __forceinline__ void wait_lgkm0() { __builtin_amdgcn_s_waitcnt(0xC07F); }
+
+// Workgroup barrier for the LDS exchanges that leaves the table loads in
+// flight (__syncthreads() would also wait for every outstanding vector
+// memory load).  Each wavefront's LDS accesses complete before it arrives;
+// the signal fences keep the compiler from moving LDS accesses across.
+__device__ __forceinline__ void lds_barrier()
+{
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    wait_lgkm0();
+    __builtin_amdgcn_s_barrier();
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+// hi/lo BF16 of one 16-row result tile: its 4 K slots of a K = 32 slab (the
+// first or second half of what split_bf16 makes of two tiles).
+__device__ __forceinline__ void split_half(const f32x4 v, bf16x4 &h, bf16x4 &l)
+{
+    bf16x2 h0, h1, l0, l1;
+    split2(v[0], v[1], h0, l0);
+    split2(v[2], v[3], h1, l1);
+    h = bf16x4{h0[0], h0[1], h1[0], h1[1]};
+    l = bf16x4{l0[0], l0[1], l1[0], l1[1]};
+}
+
+// BF16 exchange buffers: [K slab q][kind k][lane] bf16x8; 16-row tile T
+// fills half T % 2 of slab T / 2.  (In both precisions the four 16-byte
+// B operands of K slab q sit at [4 q + k][lane].)
+__device__ __forceinline__ void put_half(f32x4 *buf, int T, int k, int lane, bf16x4 v)
+{
+    reinterpret_cast<bf16x4 *>(buf + ((T >> 1) * 4 + k) * 64 + lane)[T & 1] = v;
+}
+__device__ __forceinline__ void slab4(const f32x4 *buf, int q, f32x4 *dst, int lane)
+{
+#pragma unroll
+    for (int k = 0; k < 4; ++k) dst[k] = buf[(4 * q + k) * 64 + lane];
+}
+
+template <int RT, bool BF16>
+__device__ __forceinline__ void split_tile(const BucketArgs &a, const LaunchArgs &la, int tile,
+                                           int64_t step0, f32x4 *cf, f32x4 *xb)
+{
+    constexpr int P = 4;          // wavefronts
+    constexpr int NJ = RT / P;    // mode tiles and row tiles of each
+    constexpr int KS = RT / 2;    // K slabs
+    constexpr int SF = 2 * RT;    // fragments per table stage
+    constexpr int FU = 4 * NJ;    // u = chi R fragments of one K slab for the own rows
+    // K slabs in registers: all u = chi R ones up to RT = 12 (loaded once
+    // per launch), 4 at RT = 16; the coupling ring holds the whole tile up
+    // to RT = 8, else 2 (RT = 12, beside the resident u = chi R fragments)
+    // or 4 (RT = 16, whose u = chi R ring is free during the update)
+    constexpr int DU = RT <= 12 ? KS : 4;
+    constexpr int DC = RT <= 8 ? KS : (RT == 12 ? 2 : 4);
+    static_assert(RT % P == 0 && KS % DU == 0, "split tile shape");
+    static_assert(4 * RT * 64 + 4 * RT <= kTableFrags * 64, "split tile exchange buffers");
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    {
+        const f32x4 *c4 = reinterpret_cast<const f32x4 *>(a.coef);
+        for (int i = threadIdx.x; i < kKinds * RT * 4; i += blockDim.x) cf[i] = c4[i];
+    }
+    // Rb and Gb: 2 RT fragments each ([q][k] BF16, [T][parity] FP32); cz: [J][16]
+    f32x4 *Rb = xb, *Gb = xb + 2 * RT * 64;
+    float *cz = reinterpret_cast<float *>(xb + 4 * RT * 64);
+
+    const int col = lane & 15, g = lane >> 4;
+    const int cl = col / 3, alpha = col - 3 * cl;
+    const int nvalid = min(kChainsPerTile, a.n - kChainsPerTile * tile);
+    const bool valid = (col < 15) && (cl < nvalid);
+    const uint32_t chain = valid ? (uint32_t)a.ids[kChainsPerTile * tile + cl] : 0u;
+    const float xlane = alpha == 0 ? 1.0f : 0.0f;
+    // table fragment F (1 KB): a buffer load at a scalar offset, so no
+    // per-lane 64-bit addresses are kept and only vmcnt counts it
+    const __amdgpu_buffer_rsrc_t xrs =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(a.X), 0, a.x_bytes, 0x00020000);
+    const int lane_bytes = lane * 16;
+    auto frag = [&](int F) {
+        return __builtin_bit_cast(f32x4,
+                                  __builtin_amdgcn_raw_buffer_load_b128(xrs, lane_bytes, F * 1024, 0));
+    };
+
+    f32x4 Ro[NJ], Re[NJ];
+    const f32x4 *Rt = reinterpret_cast<const f32x4 *>(a.R) + (size_t)tile * 2 * RT * 64;
+#pragma unroll
+    for (int ii = 0; ii < NJ; ++ii) {
+        const int J = wave + P * ii;
+        Ro[ii] = Rt[J * 64 + lane];
+        Re[ii] = Rt[(RT + J) * 64 + lane];
+    }
+    const bool com_lane = valid && g == 0 && wave == 0;
+    double r0 = com_lane ? a.R0[(size_t)tile * 16 + col] : 0.0;
+
+    auto put_state = [&](int ii) {
+        const int J = wave + P * ii;
+        if constexpr (BF16) {
+            bf16x4 h, l;
+            split_half(Ro[ii], h, l);
+            put_half(Rb, J, 0, lane, h);
+            put_half(Rb, J, 1, lane, l);
+            split_half(Re[ii], h, l);
+            put_half(Rb, J, 2, lane, h);
+            put_half(Rb, J, 3, lane, l);
+        } else {
+            Rb[(2 * J) * 64 + lane] = Ro[ii];
+            Rb[(2 * J + 1) * 64 + lane] = Re[ii];
+        }
+    };
+    // u = chi R fragments of K slab q for the own rows, [row tile][f]
+    f32x4 xu[DU][FU];
+    auto load_u = [&](int q, f32x4 *dst) {
+#pragma unroll
+        for (int ii = 0; ii < NJ; ++ii)
+#pragma unroll
+            for (int f = 0; f < 4; ++f)
+                dst[4 * ii + f] = frag((q * RT + wave + P * ii) * 4 + f);
+    };
+    if (la.nonlinear) {
+#pragma unroll
+        for (int ii = 0; ii < NJ; ++ii) put_state(ii);
+    }
+    __syncthreads();  // coefficients and amplitudes in LDS
+    if (la.nonlinear) {
+#pragma unroll
+        for (int q = 0; q < DU; ++q) load_u(q, xu[q]);
+    }
+
+    for (int s = 0; s < la.n_steps; ++s) {
+        const int64_t k = step0 + s;
+        float gdep = 0.0f;  // last force written: keeps the noise below the forces
+        if (la.nonlinear) {
+            // ---- u = chi R for the own half-bond row tiles
+            f32x4 aS[NJ], aA[NJ];
+#pragma unroll
+            for (int ii = 0; ii < NJ; ++ii) {
+                aS[ii] = f32x4{0.f, 0.f, 0.f, 0.f};
+                aA[ii] = f32x4{0.f, 0.f, 0.f, 0.f};
+            }
+            // B operands of slab q + 1 are read from LDS during slab q
+            f32x4 bn[4];
+            slab4(Rb, 0, bn, lane);
+#pragma unroll
+            for (int q = 0; q < KS; ++q) {
+                const f32x4 *xs = xu[q % DU];
+                f32x4 bc[4];
+#pragma unroll
+                for (int k2 = 0; k2 < 4; ++k2) bc[k2] = bn[k2];
+                if (q + 1 < KS) slab4(Rb, q + 1, bn, lane);
+                if constexpr (BF16) {
+                    const bf16x8 boh = __builtin_bit_cast(bf16x8, bc[0]);
+                    const bf16x8 bol = __builtin_bit_cast(bf16x8, bc[1]);
+                    const bf16x8 beh = __builtin_bit_cast(bf16x8, bc[2]);
+                    const bf16x8 bel = __builtin_bit_cast(bf16x8, bc[3]);
+#pragma unroll
+                    for (int ii = 0; ii < NJ; ++ii) {
+                        aS[ii] = mfma_bf16(__builtin_bit_cast(bf16x8, xs[4 * ii]), boh, aS[ii]);
+                        aA[ii] = mfma_bf16(__builtin_bit_cast(bf16x8, xs[4 * ii + 2]), beh, aA[ii]);
+                    }
+#pragma unroll
+                    for (int ii = 0; ii < NJ; ++ii) {
+                        aS[ii] = mfma_bf16(__builtin_bit_cast(bf16x8, xs[4 * ii]), bol, aS[ii]);
+                        aA[ii] = mfma_bf16(__builtin_bit_cast(bf16x8, xs[4 * ii + 2]), bel, aA[ii]);
+                    }
+#pragma unroll
+                    for (int ii = 0; ii < NJ; ++ii) {
+                        aS[ii] = mfma_bf16(__builtin_bit_cast(bf16x8, xs[4 * ii + 1]), boh, aS[ii]);
+                        aA[ii] = mfma_bf16(__builtin_bit_cast(bf16x8, xs[4 * ii + 3]), beh, aA[ii]);
+                    }
+                } else {
+#pragma unroll
+                    for (int hh = 0; hh < 2; ++hh) {
+                        const f32x4 bo = bc[2 * hh], be = bc[2 * hh + 1];
+#pragma unroll
+                        for (int r = 0; r < 4; ++r)
+#pragma unroll
+                            for (int ii = 0; ii < NJ; ++ii) {
+                                aS[ii] = mfma_f32(xs[4 * ii + hh][r], bo[r], aS[ii]);
+                                aA[ii] = mfma_f32(xs[4 * ii + 2 + hh][r], be[r], aA[ii]);
+                            }
+                    }
+                }
+                if constexpr (DU < KS) {
+                    // the next loads stay in this slab: the scheduler would
+                    // otherwise hoist them all to the top, past the registers
+                    if (q + DU < KS) load_u(q + DU, xu[q % DU]);
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            }
+            // ---- bond forces of the own rows, to LDS
+#pragma unroll
+            for (int ii = 0; ii < NJ; ++ii) {
+                const int I = wave + P * ii;
+                f32x4 Gp, Gm;
+                bond_forces(aS[ii], aA[ii], alpha, a.lin, Gp, Gm);
+                if constexpr (BF16) {
+                    bf16x4 h, l;
+                    split_half(Gp, h, l);
+                    put_half(Gb, I, 0, lane, h);
+                    put_half(Gb, I, 1, lane, l);
+                    split_half(Gm, h, l);
+                    put_half(Gb, I, 2, lane, h);
+                    put_half(Gb, I, 3, lane, l);
+                } else {
+                    Gb[(2 * I) * 64 + lane] = Gp;
+                    Gb[(2 * I + 1) * 64 + lane] = Gm;
+                }
+                gdep = Gm[0];
+            }
+            lds_barrier();  // B
+        }
+        // ---- own mode tiles: E R + W eta (+ shear) and the coupling
+#pragma unroll
+        for (int ii = 0; ii < NJ; ++ii) {
+            const int J = wave + P * ii;
+            const bool couple = la.nonlinear && J < a.jc;
+            // coupling rows of tile J, K slab q in xc[q % DC]: [odd hi, odd lo,
+            // even hi, even lo] (FP32: [odd 2q, 2q+1, even 2q, 2q+1]); the
+            // first DC slabs are in flight during the noise
+            f32x4 xc[DC][4];
+            auto load_c = [&](int q) {
+#pragma unroll
+                for (int f = 0; f < 4; ++f)
+                    xc[q % DC][f] = frag((RT + J) * SF + (f >> 1) * RT + 2 * q + (f & 1));
+            };
+            if (couple) {
+#pragma unroll
+                for (int q = 0; q < DC; ++q) load_c(q);
+            }
+            const uint32_t ch = after(chain, ii ? Ro[ii - 1][3] : (la.nonlinear ? gdep : Re[0][0]));
+            float z[8];
+            normals4_f32(noise_bits(la.seed, (uint32_t)(8 * J + 2 * g), ch, k, (uint32_t)alpha,
+                                    kTagMode),
+                         z);
+            normals4_f32(noise_bits(la.seed, (uint32_t)(8 * J + 2 * g + 1), ch, k,
+                                    (uint32_t)alpha, kTagMode),
+                         z + 4);
+            const float zn = __shfl(z[0], (lane + 16) & 63, 64);
+            if (lane < 16) cz[J * 16 + lane] = z[0];
+            const f32x4 Eo = cf[(kEo * RT + J) * 4 + g], Wo = cf[(kWo * RT + J) * 4 + g];
+            const f32x4 Ee = cf[(kEe * RT + J) * 4 + g], We = cf[(kWe * RT + J) * 4 + g];
+            f32x4 ao, ae;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const float ze = r < 3 ? z[2 * r + 2] : (g < 3 ? zn : 0.0f);
+                ao[r] = __builtin_fmaf(Eo[r], Ro[ii][r], Wo[r] * z[2 * r + 1]);
+                ae[r] = __builtin_fmaf(Ee[r], Re[ii][r], We[r] * ze);
+            }
+            if (a.gdt != 0.0) {
+                const f32x4 Go = cf[(kGo * RT + J) * 4 + g], Ge = cf[(kGe * RT + J) * 4 + g];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    ao[r] = __builtin_fmaf(Go[r], xlane * dpp<kRowShl1>(Ro[ii][r]), ao[r]);
+                    ae[r] = __builtin_fmaf(Ge[r], xlane * dpp<kRowShl1>(Re[ii][r]), ae[r]);
+                }
+            }
+            if (J == 0) {
+                const double r0y = __shfl(r0, (lane + 1) & 63, 64);
+                double nr0 = __builtin_fma(a.W0, (double)z[0], r0);
+                if (alpha == 0) nr0 = __builtin_fma(a.gdt, r0y, nr0);
+                r0 = com_lane ? nr0 : 0.0;
+            }
+            if (couple) {
+                f32x4 ce = f32x4{0.f, 0.f, 0.f, 0.f};
+                f32x4 gn[4];  // forces of slab q + 1, read during slab q
+                slab4(Gb, 0, gn, lane);
+                if constexpr (BF16) {
+                    f32x4 ao2 = f32x4{0.f, 0.f, 0.f, 0.f}, ce2 = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int q = 0; q < KS; ++q) {
+                        const bf16x8 xoh = __builtin_bit_cast(bf16x8, xc[q % DC][0]);
+                        const bf16x8 xol = __builtin_bit_cast(bf16x8, xc[q % DC][1]);
+                        const bf16x8 xeh = __builtin_bit_cast(bf16x8, xc[q % DC][2]);
+                        const bf16x8 xel = __builtin_bit_cast(bf16x8, xc[q % DC][3]);
+                        const bf16x8 gph = __builtin_bit_cast(bf16x8, gn[0]);
+                        const bf16x8 gpl = __builtin_bit_cast(bf16x8, gn[1]);
+                        const bf16x8 gmh = __builtin_bit_cast(bf16x8, gn[2]);
+                        const bf16x8 gml = __builtin_bit_cast(bf16x8, gn[3]);
+                        if (q + 1 < KS) slab4(Gb, q + 1, gn, lane);
+                        f32x4 &A = (q & 1) ? ao2 : ao;
+                        f32x4 &C = (q & 1) ? ce2 : ce;
+                        A = mfma_bf16(xoh, gph, A);
+                        C = mfma_bf16(xeh, gmh, C);
+                        A = mfma_bf16(xoh, gpl, A);
+                        C = mfma_bf16(xeh, gml, C);
+                        A = mfma_bf16(xol, gph, A);
+                        C = mfma_bf16(xel, gmh, C);
+                        if constexpr (DC < KS) {
+                            if (q + DC < KS) load_c(q + DC);
+                            __builtin_amdgcn_sched_barrier(0);
+                        }
+                    }
+                    ao += ao2;
+                    ce += ce2;
+                } else {
+#pragma unroll
+                    for (int q = 0; q < KS; ++q) {
+                        f32x4 gc[4];
+#pragma unroll
+                        for (int k2 = 0; k2 < 4; ++k2) gc[k2] = gn[k2];
+                        if (q + 1 < KS) slab4(Gb, q + 1, gn, lane);
+#pragma unroll
+                        for (int hh = 0; hh < 2; ++hh) {
+                            const f32x4 gp = gc[2 * hh], gm = gc[2 * hh + 1];
+#pragma unroll
+                            for (int r = 0; r < 4; ++r) {
+                                ao = mfma_f32(xc[q % DC][hh][r], gp[r], ao);
+                                ce = mfma_f32(xc[q % DC][2 + hh][r], gm[r], ce);
+                            }
+                        }
+                        if constexpr (DC < KS) {
+                            if (q + DC < KS) load_c(q + DC);
+                            __builtin_amdgcn_sched_barrier(0);
+                        }
+                    }
+                }
+                const f32x4 Ce = cf[(kCe * RT + J) * 4 + g];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) ae[r] = __builtin_fmaf(Ce[r], ce[r], ae[r]);
+            }
+            Ro[ii] = ao;
+            Re[ii] = ae;
+        }
+        if constexpr (DU < KS) {
+            if (la.nonlinear) {
+#pragma unroll
+                for (int q = 0; q < DU; ++q) load_u(q, xu[q]);
+            }
+        }
+        lds_barrier();  // C
+        // lane group 3's even slot r = 3 takes normal 0 of the next tile
+#pragma unroll
+        for (int ii = 0; ii < NJ; ++ii) {
+            const int J = wave + P * ii;
+            if (J + 1 < RT) {
+                const float w3 = cf[(kWe * RT + J) * 4 + g][3];
+                const float zc = cz[(J + 1) * 16 + (lane & 15)];
+                Re[ii][3] = __builtin_fmaf(g == 3 ? w3 : 0.0f, zc, Re[ii][3]);
+            }
+        }
+        if (la.nonlinear) {
+#pragma unroll
+            for (int ii = 0; ii < NJ; ++ii) put_state(ii);
+        }
+        lds_barrier();  // A (also orders this step's reads of cz before the next writes)
+    }
+    f32x4 *Rw = reinterpret_cast<f32x4 *>(a.R) + (size_t)tile * 2 * RT * 64;
+#pragma unroll
+    for (int ii = 0; ii < NJ; ++ii) {
+        const int J = wave + P * ii;
+        Rw[J * 64 + lane] = Ro[ii];
+        Rw[(RT + J) * 64 + lane] = Re[ii];
     }
     if (com_lane) a.R0[(size_t)tile * 16 + col] = r0;
 }
@@ -618,14 +1002,20 @@ __global__ __launch_bounds__(256) void fused_kernel(LaunchArgs la)
     case 6: fused_tiles<12, BF16, false>(a, la, it.tile0, step0, cf, xb); break;
     case 7: fused_tiles<14, BF16, false>(a, la, it.tile0, step0, cf, xb); break;
     case 8: fused_tiles<16, BF16, false>(a, la, it.tile0, step0, cf, xb); break;
+    case 9: split_tile<4, BF16>(a, la, it.tile0, step0, cf, xb); break;
+    case 10: split_tile<8, BF16>(a, la, it.tile0, step0, cf, xb); break;
+    case 11: split_tile<12, BF16>(a, la, it.tile0, step0, cf, xb); break;
+    case 12: split_tile<16, BF16>(a, la, it.tile0, step0, cf, xb); break;
     default: break;
     }
 }
 
 // Kernel variant of a tile shape: resident tables exist for RT <= 8,
-// streamed ones for RT >= 8.
+// streamed ones for RT >= 8, split tiles for RT = 4, 8, 12, 16.
 int variant_of(int RT, bool resident) { return resident ? RT / 2 - 1 : 4 + (RT - 8) / 2; }
 bool has_variant(int RT, bool resident) { return resident ? RT <= 8 : RT >= 8; }
+int split_variant(int RT) { return 8 + RT / 4; }
+bool has_split(int RT) { return RT >= 4 && RT <= 16 && RT % 4 == 0; }
 
 // Slot of mode p >= 1 of (local chain j, component alpha) in the state:
 // odd p at half-mode slot (p - 1)/2, even p at p/2 - 1.
@@ -1110,6 +1500,7 @@ hipError_t fused_set_coefs(FusedBucket &f, const ModeCoefs &mc, int M, double li
     f.JC = pmax > 0 ? std::min(RT, (pmax - 1) / 32 + 1) : 0;
     f.resident = fits_resident(RT, f.JC) ? 1 : 0;
     f.tpw = 4;  // default shape; timings of other coefficients are stale
+    f.split = 0;
     f.item_us = 0.0;
     hipError_t e;
     if ((e = upload_tables(f, M, mc.C.data(), st)) != hipSuccess) return e;
@@ -1130,7 +1521,7 @@ static BucketArgs bucket_args(const FusedBucket &f)
     a.ntiles = f.ntiles;
     a.x_bytes = (int)x_bytes(f.RT);
     a.jc = f.JC;
-    a.variant = variant_of(f.RT, f.resident != 0);
+    a.variant = f.split ? split_variant(f.RT) : variant_of(f.RT, f.resident != 0);
     a.tpw = f.tpw;
     a.lin = f.lin;
     a.W0 = f.W0;
@@ -1139,11 +1530,13 @@ static BucketArgs bucket_args(const FusedBucket &f)
 }
 
 // Cost model of one workgroup-step when nothing was measured: the MFMA and
-// table work grow as RT^2, the noise and forces as RT.
+// table work grow as RT^2, the noise and forces as RT; a split tile takes
+// about a third of a wavefront's time for one tile.
 static double model_us(const FusedBucket &f)
 {
     const double rt = f.RT;
-    return 0.12 * rt * rt + 0.3 * rt + (f.resident ? 0.0 : 0.02 * rt * rt);
+    const double us = 0.12 * rt * rt + 0.3 * rt + (f.resident ? 0.0 : 0.02 * rt * rt);
+    return f.split ? us / 3.0 : us;
 }
 
 double fused_item_us(const FusedBucket &f) { return f.item_us > 0.0 ? f.item_us : model_us(f); }
@@ -1205,9 +1598,10 @@ hipError_t fused_plan(FusedPlan &p, const std::vector<const FusedBucket *> &bs, 
     std::vector<BucketArgs> ba;
     for (const FusedBucket *f : bs) {
         if (f->bf16 != p.bf16) return hipErrorInvalidValue;
-        if (!has_variant(f->RT, f->resident != 0) || f->tpw < 1 || f->tpw > 4 ||
-            (!f->resident && f->tpw != 4))
-            return hipErrorInvalidValue;
+        const bool ok = f->split ? has_split(f->RT) && f->tpw == 1 && !f->resident
+                                 : has_variant(f->RT, f->resident != 0) && f->tpw >= 1 &&
+                                       f->tpw <= 4 && (f->resident || f->tpw == 4);
+        if (!ok) return hipErrorInvalidValue;
         ba.push_back(bucket_args(*f));
     }
     std::vector<Item> items = ordered_items(bs);
@@ -1271,7 +1665,7 @@ hipError_t fused_autotune(std::vector<FusedBucket *> &bs, uint64_t seed, int ste
         return e;
     if (steps < 1) steps = 64;
     struct Cand {
-        int resident, tpw;
+        int resident, tpw, split;
         double us;  // per workgroup-step
     };
     std::vector<std::vector<Cand>> cands(bs.size());
@@ -1299,13 +1693,15 @@ hipError_t fused_autotune(std::vector<FusedBucket *> &bs, uint64_t seed, int ste
             if (!has_variant(f.RT, res) || (res && !fits_resident(f.RT, f.JC))) continue;
             for (int tpw : {4, 2, 1}) {
                 if (!res && tpw != 4) continue;
-                list.push_back({res, tpw, 0.0});
+                list.push_back({res, tpw, 0, 0.0});
             }
         }
+        if (has_split(f.RT)) list.push_back({0, 1, 1, 0.0});
         for (Cand &c : list) {
             if (e != hipSuccess) break;
             t.resident = c.resident;
             t.tpw = c.tpw;
+            t.split = c.split;
             t.item_us = 0.0;
             FusedPlan p;
             // at most one workgroup per CU: the time of one item
@@ -1360,6 +1756,8 @@ hipError_t fused_autotune(std::vector<FusedBucket *> &bs, uint64_t seed, int ste
             }
         }
     } else {
+        // from each bucket's cheapest shape per tile, change one bucket at a
+        // time while the makespan shrinks
         for (size_t b = 0; b < bs.size(); ++b) {
             double best = 1e300;
             for (size_t c = 0; c < cands[b].size(); ++c) {
@@ -1370,6 +1768,23 @@ hipError_t fused_autotune(std::vector<FusedBucket *> &bs, uint64_t seed, int ste
                 }
             }
         }
+        double cur_m = evaluate(pick);
+        for (int pass = 0; pass < 8; ++pass) {
+            bool improved = false;
+            for (size_t b = 0; b < bs.size(); ++b)
+                for (size_t c = 0; c < cands[b].size(); ++c) {
+                    if ((int)c == pick[b]) continue;
+                    std::vector<int> trial = pick;
+                    trial[b] = (int)c;
+                    const double m = evaluate(trial);
+                    if (m < cur_m) {
+                        cur_m = m;
+                        pick = trial;
+                        improved = true;
+                    }
+                }
+            if (!improved) break;
+        }
     }
     char line[256];
     report.clear();
@@ -1378,11 +1793,13 @@ hipError_t fused_autotune(std::vector<FusedBucket *> &bs, uint64_t seed, int ste
         const Cand &c = cands[b][pick[b]];
         f.resident = c.resident;
         f.tpw = c.tpw;
+        f.split = c.split;
         f.item_us = c.us;
         for (size_t k = 0; k < cands[b].size(); ++k) {
+            const Cand &ck = cands[b][k];
             snprintf(line, sizeof line, "RT=%d %s tpw=%d: %.2f us/step%s\n", f.RT,
-                     cands[b][k].resident ? "resident" : "streamed", cands[b][k].tpw,
-                     cands[b][k].us, (int)k == pick[b] ? "  <- chosen" : "");
+                     ck.split ? "split" : (ck.resident ? "resident" : "streamed"), ck.tpw, ck.us,
+                     (int)k == pick[b] ? "  <- chosen" : "");
             report += line;
         }
     }
@@ -1393,10 +1810,17 @@ void fused_force_shape(FusedBucket &f, int table_mode, int tpw)
 {
     if (table_mode == 1 && has_variant(f.RT, true) && fits_resident(f.RT, f.JC)) {
         f.resident = 1;
+        f.split = 0;
         f.item_us = 0.0;
     } else if (table_mode == 2 && has_variant(f.RT, false)) {
         f.resident = 0;
+        f.split = 0;
         f.tpw = 4;
+        f.item_us = 0.0;
+    } else if (table_mode == 3 && has_split(f.RT)) {
+        f.resident = 0;
+        f.split = 1;
+        f.tpw = 1;
         f.item_us = 0.0;
     }
     if (tpw >= 1 && tpw <= 4 && f.resident) {

@@ -124,3 +124,72 @@ def test_graph_replays_single_length_benchmark_shape():
             out.append((c.modes(), c.accumulators()[0]))
     assert np.array_equal(out[0][0], out[1][0])
     assert out[0][1]["L2"] == out[1][1]["L2"] and out[0][1]["n_samples"] == 3
+
+
+# Split tiles: one tile of 5 chains per workgroup, its bond rows and mode
+# tiles divided among 4 wavefronts that exchange amplitudes, forces and one
+# normal per tile through LDS.  Each accumulator sees the same products in
+# the same order as with one wavefront per tile, so the states agree bit for
+# bit.  Lengths with RT = 4 (96, 128 beads), 8 (256), 12 (384), 16 (512).
+SPLIT_LENS = [96, 128, 256, 384, 512]
+SPLIT_DTAU = {96: 10.0, 128: 50.0, 256: 100.0, 384: 100.0, 512: 100.0}
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("kw", [{}, {"gamma_dot": 3e-6}, {"nonlinear": False}],
+                         ids=["nonlinear", "shear", "linear"])
+def test_split_tiles_bit_identical_to_one_wavefront_per_tile(prec, kw):
+    beads = inputs.mixed_lengths(61, SPLIT_LENS, seed=3)  # ragged last tiles
+    chains = inputs.mixed_chains(beads, B_FAC, seed=3)
+    runs = {}
+    for mode in ("split", "resident", "streamed"):
+        with Context(chains, seed=4, precision=prec) as ctx:
+            ctx.set_params(SPLIT_LENS, [SPLIT_DTAU[m] for m in SPLIT_LENS], T_star=TS, nu=NU,
+                           table_mode=mode, **kw)
+            til = ctx.tiling()
+            ctx.step_modes(7)
+            runs[mode] = (ctx.modes(), til)
+    print(prec, kw, [(int(t["M"]), int(t["RT"]), int(t["JC"]), int(t["split"]))
+                     for t in runs["split"][1]])
+    assert all(int(t["split"]) == 1 and int(t["items"]) == -(-int(t["n_chains"]) // 5)
+               for t in runs["split"][1])
+    assert all(int(t["split"]) == 0 for m in ("resident", "streamed") for t in runs[m][1])
+    assert same(runs["split"][0], runs["resident"][0])
+    assert same(runs["split"][0], runs["streamed"][0])
+
+
+@pytest.mark.parametrize("B,M,dtau", [(1024, 128, 50.0), (1024, 512, 100.0)])
+def test_split_tiles_at_batched_sizes(B, M, dtau):
+    """The 1024-chain configurations, where the automatic shape (fewer tiles
+    than compute units) is the split tile."""
+    pos = inputs.straight_chains(B, M, B_FAC, seed=1, random_orientation=True)
+    out = []
+    for mode in ("auto", "streamed" if M > 256 else "resident"):
+        with Context(pos, seed=1, precision="bf16x3") as c:
+            c.set_params([M], [dtau], T_star=TS, nu=NU, table_mode=mode)
+            assert int(c.tiling()[0]["split"]) == (1 if mode == "auto" else 0)
+            c.step_modes(5)
+            out.append(c.modes())
+    assert same(out[0], out[1])
+
+
+def test_split_tiles_graph_replays_and_observables():
+    """Split tiles under replayed sampling blocks: states and accumulators
+    equal to the eager run of the other shape."""
+    B, M = 300, 256
+    pos = inputs.straight_chains(B, M, B_FAC, seed=6, random_orientation=True)
+    res = []
+    for mode, graphs in (("split", True), ("resident", False)):
+        with Context(pos, seed=6, precision="bf16x3") as c:
+            c.set_params([M], [100.0], T_star=TS, nu=NU, sample_every=10, use_graphs=graphs,
+                         table_mode=mode, corr_lags=3)
+            c.step_modes(45)
+            c.step_modes(30)
+            res.append((c.modes(), c.accumulators()[0]))
+    assert same(res[0][0], res[1][0])
+    a, b = res[0][1], res[1][1]
+    assert a["n_samples"] == b["n_samples"] == 7
+    for k in ("bond", "L2", "msd_cm"):
+        assert a[k] == b[k], k
+    assert np.array_equal(a["modes"], b["modes"])
+    assert np.array_equal(a["corr"], b["corr"])
