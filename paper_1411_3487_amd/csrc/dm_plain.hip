@@ -87,23 +87,32 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const double *__restrict_
 // pipeline over the K chunks -- the next chunk is loaded into registers while
 // the current one is multiplied from the other of two LDS buffers, one
 // barrier per chunk.  The MFMA sequence of every accumulator is the one of
-// the kernel above, so both give the same bits.
+// the kernel above, so both give the same bits.  BN = 64 or 32 columns per
+// workgroup tile (each wavefront 32 rows x BN/2 columns): the narrower tile
+// doubles the workgroups of small launches (1024 chains of 128 beads make 96
+// tiles of 64 x 64 for 256 CUs) and leaves every accumulator's sequence as it
+// is.
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 
+template <int BN>
 __global__ __launch_bounds__(256) void gemm_f64_pipe_kernel(const double *__restrict__ A,
                                                             const double *__restrict__ X,
                                                             double *__restrict__ Y, int M,
                                                             int ncol)
 {
+    static_assert(BN == 64 || BN == 32, "column tile");
+    constexpr int TJ = BN / 32;  // 16-column MFMA tiles per wavefront
     __shared__ double As[2][kGemmBM][kGemmBK + 1];
-    __shared__ double Xs[2][kGemmBN][kGemmBK + 1];
+    __shared__ double Xs[2][BN][kGemmBK + 1];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wi = wave >> 1, wj = wave & 1;
     const int i0 = blockIdx.x * kGemmBM;
-    const int c0 = blockIdx.y * kGemmBN;
-    // each thread moves 4 consecutive k of one row of A and one column of X
+    const int c0 = blockIdx.y * BN;
+    // each thread moves 4 consecutive k of one row of A and (lr < BN) of one
+    // column of X
     const int lr = tid >> 2, lk = (tid & 3) * 4;
-    const bool arow = i0 + lr < M, xrow = c0 + lr < ncol;
+    const bool xown = lr < BN;
+    const bool arow = i0 + lr < M, xrow = xown && c0 + lr < ncol;
     const f64x2 *pa = reinterpret_cast<const f64x2 *>(A + (size_t)(arow ? i0 + lr : 0) * M + lk);
     const f64x2 *px = reinterpret_cast<const f64x2 *>(X + (size_t)(xrow ? c0 + lr : 0) * M + lk);
     f64x2 ra0, ra1, rx0, rx1;
@@ -119,16 +128,18 @@ __global__ __launch_bounds__(256) void gemm_f64_pipe_kernel(const double *__rest
         As[b][lr][lk + 1] = ra0[1];
         As[b][lr][lk + 2] = ra1[0];
         As[b][lr][lk + 3] = ra1[1];
-        Xs[b][lr][lk] = rx0[0];
-        Xs[b][lr][lk + 1] = rx0[1];
-        Xs[b][lr][lk + 2] = rx1[0];
-        Xs[b][lr][lk + 3] = rx1[1];
+        if (xown) {
+            Xs[b][lr][lk] = rx0[0];
+            Xs[b][lr][lk + 1] = rx0[1];
+            Xs[b][lr][lk + 2] = rx1[0];
+            Xs[b][lr][lk + 3] = rx1[1];
+        }
     };
-    f64x4 acc[2][2];
+    f64x4 acc[2][TJ];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+        for (int b = 0; b < TJ; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
 
     const int nk = M / kGemmBK;
     load(0);
@@ -139,16 +150,17 @@ __global__ __launch_bounds__(256) void gemm_f64_pipe_kernel(const double *__rest
         if (kt + 1 < nk) load((kt + 1) * kGemmBK);
 #pragma unroll
         for (int ks = 0; ks < kGemmBK; ks += 4) {
-            double a[2], x[2];
+            double a[2], x[TJ];
 #pragma unroll
-            for (int t = 0; t < 2; ++t) {
+            for (int t = 0; t < 2; ++t)
                 a[t] = As[b][32 * wi + 16 * t + (lane & 15)][ks + (lane >> 4)];
-                x[t] = Xs[b][32 * wj + 16 * t + (lane & 15)][ks + (lane >> 4)];
-            }
+#pragma unroll
+            for (int t = 0; t < TJ; ++t)
+                x[t] = Xs[b][(BN / 2) * wj + 16 * t + (lane & 15)][ks + (lane >> 4)];
 #pragma unroll
             for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
-                for (int tj = 0; tj < 2; ++tj)
+                for (int tj = 0; tj < TJ; ++tj)
                     acc[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ti], x[tj],
                                                                       acc[ti][tj], 0, 0, 0);
         }
@@ -158,8 +170,8 @@ __global__ __launch_bounds__(256) void gemm_f64_pipe_kernel(const double *__rest
 #pragma unroll
     for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
-        for (int tj = 0; tj < 2; ++tj) {
-            const int c = c0 + 32 * wj + 16 * tj + (lane & 15);
+        for (int tj = 0; tj < TJ; ++tj) {
+            const int c = c0 + (BN / 2) * wj + 16 * tj + (lane & 15);
             const int ib = i0 + 32 * wi + 16 * ti + (lane >> 4);
             if (c >= ncol) continue;
 #pragma unroll
@@ -1019,10 +1031,20 @@ hipError_t launch_gemm_f64(const double *A, const double *X, double *Y, int M, i
 {
     if (M <= 0 || ncol <= 0) return hipSuccess;
     dim3 grid((M + kGemmBM - 1) / kGemmBM, (ncol + kGemmBN - 1) / kGemmBN);
-    if (M % kGemmBK == 0)
-        hipLaunchKernelGGL(gemm_f64_pipe_kernel, grid, dim3(256), 0, st, A, X, Y, M, ncol);
-    else
+    if (M % kGemmBK == 0) {
+        // narrower column tiles while 64 x 64 tiles would not give every CU
+        // of the GPU two workgroups
+        if (grid.x * grid.y < 512) {
+            grid.y = (ncol + 31) / 32;
+            hipLaunchKernelGGL(gemm_f64_pipe_kernel<32>, grid, dim3(256), 0, st, A, X, Y, M,
+                               ncol);
+        } else {
+            hipLaunchKernelGGL(gemm_f64_pipe_kernel<64>, grid, dim3(256), 0, st, A, X, Y, M,
+                               ncol);
+        }
+    } else {
         hipLaunchKernelGGL(gemm_f64_kernel, grid, dim3(256), 0, st, A, X, Y, M, ncol);
+    }
     return hipGetLastError();
 }
 

@@ -183,29 +183,32 @@ def test_fused_observables_match_fp64_of_the_same_state(prec, M):
     assert np.allclose(m2, want_m2, rtol=2e-6, atol=1e-12 * want_m2.max())
 
 
-def test_benchmark_launch_configuration_at_full_size():
-    """4096 x 256 bp, split BF16, in the launch configuration the benchmark
-    times: autotuned tile shapes, sampling blocks of 100 steps replayed as
-    graphs with the observables of each block taken beside the next launch.
-    After 300 steps, sampled chains are recomputed by the oracle one by one:
-    positions, and the per-chain observables of the final state, which the
-    last (eager) observation wrote."""
-    B, M, n = 4096, 256, 300
+@pytest.mark.parametrize("B,M,dtau,n", [(4096, 256, 100.0, 300), (1024, 128, 50.0, 300),
+                                        (1024, 512, 100.0, 200)])
+def test_benchmark_launch_configuration_at_full_size(B, M, dtau, n):
+    """Split BF16 in the launch configuration the benchmark times: autotuned
+    tile shapes (4-tile workgroups at 4096 x 256, split tiles at 1024
+    chains), sampling blocks of 100 steps replayed as graphs with the
+    observables of each block taken beside the next launch where CUs are
+    spare.  Afterwards sampled chains are recomputed by the oracle one by
+    one: positions, and the per-chain observables of the final state, which
+    the last (eager) observation wrote."""
     pos = inputs.straight_chains(B, M, B_FAC, seed=1, random_orientation=True)
     with Context(pos, seed=1, precision="bf16x3") as ctx:
-        ctx.set_params([M], [100.0], T_star=TS, nu=NU, sample_every=100, use_graphs=True,
+        ctx.set_params([M], [dtau], T_star=TS, nu=NU, sample_every=100, use_graphs=True,
                        autotune=True)
+        print(ctx.tiling()[0])
         ctx.step_modes(n)
         got = ctx.positions()
         obs = ctx.chain_observables()
         acc = ctx.accumulators()[0]
-    assert acc["n_samples"] == 3 and acc["n_chains"] == B
-    for c in [0, 4, 5, 1027, 2048, 4095]:
-        R = oracle.step_modes(oracle.modes_from_positions(pos[c][None]), NU, TS, 100.0, n,
+    assert acc["n_samples"] == n // 100 and acc["n_chains"] == B
+    for c in [0, 4, 5, B // 4 + 3, B // 2, B - 1]:
+        R = oracle.step_modes(oracle.modes_from_positions(pos[c][None]), NU, TS, dtau, n,
                               seed=1, chain_ids=[c])
         want = oracle.positions_from_modes(R)
         err = rel_pos_err(got[c][None], want)
-        print(f"chain {c}: 300-step rel err {err:.2e}")
+        print(f"chain {c}: {n}-step rel err {err:.2e}")
         assert err < 1e-4, (c, err)
         o = oracle.chain_observables(want)[0]
         L = (M - 1) * B_FAC
