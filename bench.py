@@ -41,12 +41,18 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1000)
     ap.add_argument("--precision", default="bf16x3", choices=["bf16x3", "fp32"])
     ap.add_argument("--chains", type=int, default=4096)
+    ap.add_argument("--uneven-chains", type=int, default=8192,
+                    help="chains of the uneven workload (1024: one GPU's share of 8192 on 8)")
     ap.add_argument("--beads", type=int, default=256)
     ap.add_argument("--dtau", type=float, default=100.0)
     ap.add_argument("--sample-every", type=int, default=100)
     ap.add_argument("--no-graphs", action="store_true", help="eager launches instead of "
                     "replayed graphs of the sampling blocks")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--table-mode", default="auto",
+                    choices=["auto", "resident", "streamed", "split"],
+                    help="force a tile shape of the fused launch where it exists (modes and "
+                         "uneven workloads; overrides the autotuner)")
     ap.add_argument("--fp64-steps", type=int, default=500)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1024,
@@ -130,15 +136,16 @@ DTAU_OF = {64: 10.0, 96: 10.0, 128: 50.0, 192: 50.0, 256: 100.0, 384: 100.0, 512
 
 
 def uneven_workload(args):
-    """8192 chains with lengths uniform over LENGTHS (seed 2), each at its
-    length's time step, advanced in one fused launch per sampling block."""
+    """--uneven-chains chains (8192) with lengths uniform over LENGTHS (seed
+    2), each at its length's time step, advanced in one fused launch per
+    sampling block."""
     import numpy as np
     import torch
     from paper_1411_3487_amd import Context, inputs, NU_DSDNA, T_STAR_DSDNA
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
     b = 1.0 / (1.0 - 2.0 * NU_DSDNA)
-    B = 8192
+    B = args.uneven_chains
     beads = inputs.mixed_lengths(B, LENGTHS, seed=2)
     chains = inputs.mixed_chains(beads, b, seed=2)
     steps = args.steps if args.steps != 20000 else 4000
@@ -146,7 +153,7 @@ def uneven_workload(args):
     ctx = Context(chains, seed=2, precision=args.precision, stream=stream)
     ctx.set_params(LENGTHS, dts, T_star=T_STAR_DSDNA, nu=NU_DSDNA,
                    sample_every=args.sample_every, use_graphs=not args.no_graphs,
-                   autotune=not args.no_autotune)
+                   autotune=not args.no_autotune, table_mode=args.table_mode)
     tiling, report = ctx.tiling(), ctx.tuning_report()
     ctx.step_modes(min(args.warmup, 500))
     torch.cuda.synchronize()
@@ -170,7 +177,8 @@ def uneven_workload(args):
         "data": "synthetic",
         "config": {"workload": f"{B} chains, lengths uniform over {LENGTHS} bp (seed 2), "
                                f"dtau {dts}, observables every {args.sample_every} steps",
-                   "graphs": not args.no_graphs, "autotune": not args.no_autotune},
+                   "graphs": not args.no_graphs, "autotune": not args.no_autotune,
+                   "table_mode": args.table_mode},
         "bead_steps_per_s": rate * float(np.mean(beads)),
         "fp64_plain_chain_steps_per_s": B * 200 / t64,
         "speedup_vs_fp64_plain": rate / (B * 200 / t64),
@@ -657,7 +665,7 @@ def main():
     ctx = Context(pos, seed=1, precision=args.precision, stream=stream)
     ctx.set_params([M], [args.dtau], T_star=T_STAR_DSDNA, nu=NU_DSDNA,
                    sample_every=args.sample_every, use_graphs=not args.no_graphs,
-                   autotune=not args.no_autotune)
+                   autotune=not args.no_autotune, table_mode=args.table_mode)
     tiling, report = ctx.tiling()[0], ctx.tuning_report()
     shape = "split" if tiling["split"] else ("resident" if tiling["resident"] else "streamed")
     ctx.step_modes(args.warmup)
