@@ -41,6 +41,11 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1000)
     ap.add_argument("--precision", default="bf16x3", choices=["bf16x3", "fp32"])
     ap.add_argument("--chains", type=int, default=4096)
+    ap.add_argument("--dtmax-lengths", default="64,128,256",
+                    help="chain lengths (beads) of the dtmax workload; 512 is N = 511")
+    ap.add_argument("--dtmax-dtaus", default="",
+                    help="time steps of the dtmax workload (comma list), instead of each "
+                         "length's default bracket")
     ap.add_argument("--uneven-chains", type=int, default=8192,
                     help="chains of the uneven workload (1024: one GPU's share of 8192 on 8)")
     ap.add_argument("--beads", type=int, default=256)
@@ -356,6 +361,21 @@ def euler_workload(args):
     print(json.dumps(out))
 
 
+def steps_with_progress(ctx, n, label, chunk=2_000_000):
+    """ctx.step_modes(n) in pieces, with a progress line to stderr after
+    each (long runs at N = 511 take minutes)."""
+    import torch
+    t0, done = time.perf_counter(), 0
+    while done < n:
+        k = min(chunk, n - done)
+        ctx.step_modes(k)
+        done += k
+        if n > chunk:
+            torch.cuda.synchronize()
+            print(f"# {label}: {done}/{n} steps, {time.perf_counter() - t0:.0f} s",
+                  file=sys.stderr, flush=True)
+
+
 def dtmax_workload(args):
     """Equilibrium values Q(0) of the mode dynamics (Sec. 6: <L^2>, middle
     bead about the centre of mass, bond moments) for several time steps,
@@ -367,28 +387,38 @@ def dtmax_workload(args):
     from paper_1411_3487_amd import Context, inputs, NU_DSDNA, T_STAR_DSDNA
     torch.cuda.set_device(0)
     b = 1.0 / (1.0 - 2.0 * NU_DSDNA)
-    # time steps bracketing the paper's Table 1 (50, 100, 100 at N = 63, 127,
-    # 255); Monte Carlo burn-in and sampling sweeps
+    # time steps bracketing the paper's Table 1 (50, 100, 100, 100 at N = 63,
+    # 127, 255, 511); Monte Carlo burn-in and sampling sweeps
     plan = {64: ([1, 10, 20, 50, 100, 200, 500], 3000, 6000),
             128: ([10, 50, 100, 200, 500, 1000], 8000, 12000),
-            256: ([100, 200, 500, 1000, 2000], 20000, 20000)}
+            256: ([100, 200, 500, 1000, 2000], 20000, 20000),
+            512: ([100, 200, 500], 20000, 20000)}
+    lengths = [int(x) for x in args.dtmax_lengths.split(",") if x]
+    if any(M not in plan for M in lengths):
+        raise SystemExit(f"dtmax lengths must be among {sorted(plan)}")
     B = 1024
     keys = ("L2", "dmid2", "bond", "bond2")
     out = []
-    for M, (dts, burn, samp) in plan.items():
+    for M in lengths:
+        dts, burn, samp = plan[M]
+        if args.dtmax_dtaus:
+            dts = [float(x) for x in args.dtmax_dtaus.split(",") if x]
         pos = inputs.straight_chains(B, M, b, seed=M, random_orientation=True)
         t0 = time.perf_counter()
         mc = Context(pos, seed=M, precision="fp64")
         mc.set_params([M], [1.0], T_star=T_STAR_DSDNA, nu=NU_DSDNA, sample_every=20)
-        mc.step_mc(burn)
-        state = mc.positions()
-        mc.accumulators(reset=True)
-        mc.step_mc(samp)
+        for phase, sweeps in (("burn-in", burn), ("sampling", samp)):
+            if phase == "sampling":
+                state = mc.positions()
+                mc.accumulators(reset=True)
+            for k0 in range(0, sweeps, 5000):
+                mc.step_mc(min(5000, sweeps - k0))
+                torch.cuda.synchronize()
+                print(f"# M={M}: Monte Carlo {phase} {min(k0 + 5000, sweeps)}/{sweeps} sweeps, "
+                      f"{time.perf_counter() - t0:.0f} s", file=sys.stderr, flush=True)
         a = mc.accumulators()[0]
         ref = {k: a[k] / a["n_samples"] for k in keys}
         mc.close()
-        print(f"# M={M}: Monte Carlo {burn}+{samp} sweeps, {time.perf_counter() - t0:.0f} s",
-              file=sys.stderr, flush=True)
         z1 = 16 * NU_DSDNA * np.sin(np.pi / (2 * M)) ** 4
         rows = []
         for dt in dts:
@@ -397,9 +427,9 @@ def dtmax_workload(args):
             ctx = Context(state, seed=M + 1, precision=args.precision)
             ctx.set_params([M], [float(dt)], T_star=T_STAR_DSDNA, nu=NU_DSDNA,
                            sample_every=max(1, n // 400), use_graphs=True)
-            ctx.step_modes(n)
+            steps_with_progress(ctx, n, f"M={M} dtau={dt} relax")
             ctx.accumulators(reset=True)
-            ctx.step_modes(n)
+            steps_with_progress(ctx, n, f"M={M} dtau={dt} average")
             d = ctx.accumulators()[0]
             ctx.close()
             ratio = {k: d[k] / d["n_samples"] / ref[k] for k in keys}
