@@ -463,14 +463,26 @@ def dtmax_t_workload(args):
     #     Monte Carlo burn-in sweeps)
     plan = {64: ([0.1, 1, 10, 20, 50, 100], 100.0, 2.0e6, [100, 1e3, 1e4, 1e5], 3000),
             128: ([1, 10, 50, 100, 200], 1000.0, 2.0e7, [1e3, 1e4, 1e5, 1e6], 8000),
-            256: ([10, 100, 200, 500], 1.0e4, 1.0e8, [1e4, 1e5, 1e6, 1e7], 20000)}
+            256: ([10, 100, 200, 500], 1.0e4, 1.0e8, [1e4, 1e5, 1e6, 1e7], 20000),
+            512: ([10, 100, 200, 500], 1.0e5, 5.0e8, [1e5, 1e6, 1e7, 1e8], 20000)}
+    lengths = [int(x) for x in args.dtmax_lengths.split(",") if x]
+    if any(M not in plan for M in lengths):
+        raise SystemExit(f"dtmax_t lengths must be among {sorted(plan)}")
     names = ("L", "umid", "msd")
     out = []
-    for M, (dts, ts, run, times, burn) in plan.items():
+    for M in lengths:
+        dts, ts, run, times, burn = plan[M]
+        if args.dtmax_dtaus:  # the first one is the reference
+            dts = [float(x) for x in args.dtmax_dtaus.split(",") if x]
         pos = inputs.straight_chains(B, M, b, seed=M, random_orientation=True)
         mc = Context(pos, seed=M, precision="fp64")
         mc.set_params([M], [1.0], T_star=T_STAR_DSDNA, nu=NU_DSDNA)
-        mc.step_mc(burn)
+        t0 = time.perf_counter()
+        for k0 in range(0, burn, 5000):
+            mc.step_mc(min(5000, burn - k0))
+            torch.cuda.synchronize()
+            print(f"# M={M}: Monte Carlo {min(k0 + 5000, burn)}/{burn} sweeps, "
+                  f"{time.perf_counter() - t0:.0f} s", file=sys.stderr, flush=True)
         state = mc.positions()
         mc.close()
         lags = np.array([0.0] + [ts * 2 ** (j - 1) for j in range(1, K)])
@@ -482,7 +494,7 @@ def dtmax_t_workload(args):
             ctx = Context(state, seed=M + 2, precision=args.precision)
             ctx.set_params([M], [float(dt)], T_star=T_STAR_DSDNA, nu=NU_DSDNA,
                            sample_every=se, corr_lags=K, use_graphs=True)
-            ctx.step_modes(n)
+            steps_with_progress(ctx, n, f"M={M} dtau={dt}", chunk=max(se, 2_000_000 // se * se))
             c = ctx.accumulators()[0]["corr"][:K]
             ctx.close()
             q = c[:, :3] / np.maximum(c[:, 3:4], 1)
