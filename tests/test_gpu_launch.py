@@ -193,3 +193,20 @@ def test_split_tiles_graph_replays_and_observables():
         assert a[k] == b[k], k
     assert np.array_equal(a["modes"], b["modes"])
     assert np.array_equal(a["corr"], b["corr"])
+
+
+def test_table_mode_split_where_it_exists_and_bad_modes_rejected():
+    """table_mode = 3 puts the lengths with RT = 4, 8, 12, 16 on split tiles
+    and leaves the others on their default shape; 4 is rejected."""
+    from paper_1411_3487_amd import DMError
+    beads, chains = uneven(40)
+    with Context(chains, seed=2, precision="bf16x3") as ctx:
+        with pytest.raises(DMError):
+            ctx.set_params(LENS, [DTAU[m] for m in LENS], T_star=TS, nu=NU, table_mode=4)
+        ctx.set_params(LENS, [DTAU[m] for m in LENS], T_star=TS, nu=NU, table_mode="split")
+        til = ctx.tiling()
+        assert [int(t["RT"]) for t in til] == [2, 4, 4, 6, 8, 12, 16]
+        assert [int(t["split"]) for t in til] == [0, 1, 1, 0, 1, 1, 1]
+        assert all(int(t["tpw"]) == 1 and int(t["resident"]) == 0 for t in til if t["split"])
+        ctx.step_modes(3)
+        assert np.all(np.isfinite(ctx.chain_observables()))
