@@ -491,6 +491,66 @@ def test_chain_observables_of_a_straight_chain():
     assert names["xspan"] == pytest.approx(0.6 * (M - 1) * s)
 
 
+@pytest.mark.parametrize("M", [2, 3, 64, 255])
+def test_modes_from_positions_is_the_orthonormal_dct2(M):
+    """Eq. (c1) with the orthonormal modes of Eq. (c8): R_p = sum_n phi_{n,p} r_n
+    is scipy's orthonormal DCT-II of each coordinate row (random chains, so
+    a transposed phi or an index shifted by one changes the result)."""
+    rng = np.random.default_rng(100 + M)
+    pos = rng.standard_normal((4, 3, M)) * 3.0 + np.arange(M)[None, None, :]
+    expect = scipy.fft.dct(pos, type=2, norm="ortho", axis=-1)
+    got = oracle.modes_from_positions(pos)
+    assert np.abs(got - expect).max() < 1e-12 * max(1.0, np.abs(expect).max())
+    back = oracle.positions_from_modes(got)
+    assert np.abs(back - pos).max() < 1e-12 * max(1.0, np.abs(pos).max())
+
+
+def _irregular_chain(M, seed):
+    """A chain whose bonds all differ in length and direction."""
+    rng = np.random.default_rng(seed)
+    u = rng.standard_normal((3, M - 1))
+    u *= (0.5 + np.arange(M - 1) / (M - 1))[None, :] / np.linalg.norm(u, axis=0)
+    pos = np.zeros((3, M))
+    pos[:, 1:] = np.cumsum(u, axis=1)
+    return pos + rng.standard_normal((3, 1))
+
+
+@pytest.mark.parametrize("M", [2, 3, 8, 9, 64, 65])
+def test_chain_observables_of_an_irregular_chain(M):
+    """Observables of Sec. V.B on a chain with all bonds distinct, written
+    out from their definitions with numpy: the middle bond is the bond with
+    as many bonds before it as after it (unique for an odd bond count, even
+    M), the middle bead likewise (unique for odd M); for the other parity the
+    lower of the two central ones is taken."""
+    pos = _irregular_chain(M, seed=7 * M)
+    o = dict(zip(oracle.OBS_NAMES, oracle.chain_observables(pos[None])[0]))
+    bonds = [pos[:, i + 1] - pos[:, i] for i in range(M - 1)]
+    lengths = np.array([np.sqrt(b @ b) for b in bonds])
+    assert o["bond_mean"] == pytest.approx(lengths.sum() / (M - 1), rel=1e-13)
+    assert o["bond2_mean"] == pytest.approx((lengths ** 2).sum() / (M - 1), rel=1e-13)
+    L = pos[:, M - 1] - pos[:, 0]
+    assert np.allclose([o["Lx"], o["Ly"], o["Lz"]], L, rtol=0, atol=1e-13)
+    assert o["L2"] == pytest.approx(L @ L, rel=1e-13)
+    cm = pos.sum(axis=1) / M
+    assert np.allclose([o["cmx"], o["cmy"], o["cmz"]], cm, rtol=0, atol=1e-13)
+    # middle bond: bonds 0..N-1 (N = M-1), k before and N-1-k after it
+    N = M - 1
+    k_mid = [k for k in range(N) if k == N - 1 - k] or [N // 2 - 1]
+    assert np.allclose([o["umx"], o["umy"], o["umz"]], bonds[k_mid[0]], rtol=0, atol=1e-13)
+    # middle bead: beads 0..M-1, j before and M-1-j after it
+    j_mid = [j for j in range(M) if j == M - 1 - j] or [M // 2 - 1]
+    assert np.allclose([o["dmx"], o["dmy"], o["dmz"]], pos[:, j_mid[0]] - cm, rtol=0,
+                       atol=1e-13)
+    assert o["xspan"] == pytest.approx(pos[0].max() - pos[0].min(), rel=1e-13)
+    # the pin distinguishes neighbouring indices
+    if M > 2:
+        for k in (k_mid[0] - 1, k_mid[0] + 1):
+            if 0 <= k < N:
+                assert not np.allclose([o["umx"], o["umy"], o["umz"]], bonds[k])
+        for j in (j_mid[0] - 1, j_mid[0] + 1):
+            assert not np.allclose([o["dmx"], o["dmy"], o["dmz"]], pos[:, j] - cm)
+
+
 # ---------------------------------------------------------------- tumbling
 def test_tumbles_of_a_uniform_rotation():
     """(L_x, L_y) turning at one revolution per 1000 steps, sampled every
