@@ -27,13 +27,16 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--workload", default="modes",
-                    choices=["modes", "uneven", "shear", "mc", "dtmax", "dtmax_t", "wlc", "euler"],
+                    choices=["modes", "uneven", "shear", "mc", "dtmax", "dtmax_t", "wlc", "euler",
+                             "stats"],
                     help="modes: 4096 x 256 bp (the headline line); uneven: 8192 chains of "
                          "64..512 bp in one launch; shear: 2048 x 256 bp under simple shear "
                          "at Wi = 1, 10, 100 (tumbling and extension, FP32 vs FP64); mc: "
                          "Metropolis sweeps of 4096 x 256 bp; dtmax: equilibrium values of the "
                          "mode dynamics against Monte Carlo over a range of time steps")
     ap.add_argument("--shear-steps", type=int, default=1000000)
+    ap.add_argument("--stats-steps", type=int, default=100000,
+                    help="steps of each run of the stats workload")
     ap.add_argument("--profile-launches", type=int, default=0, metavar="N",
                     help="only run N fused launches of 200 steps of the default workload "
                          "(for hardware-counter passes) and exit")
@@ -107,6 +110,20 @@ def executed_flops(precision, M, jc):
     return (3.0 if precision == "bf16x3" else 1.0) * (3.0 * M * M + 3.0 * rows * M)
 
 
+def host_cpu():
+    """CPU model name and logical CPU count of this host (from /proc/cpuinfo)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "logical_cpus": os.cpu_count()}
+
+
 def cpu_baseline(args, pos, nu, ts):
     import numpy as np
     import oracle
@@ -118,6 +135,7 @@ def cpu_baseline(args, pos, nu, ts):
                       chain_ids=np.arange(sub.shape[0]))
     dt = time.perf_counter() - t0
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    host = host_cpu()
     # one core: the figure to set beside the paper's single-chain desktop runs
     one = sub[:32]
     R1 = oracle.modes_from_positions(one)
@@ -129,7 +147,8 @@ def cpu_baseline(args, pos, nu, ts):
     finally:
         oracle.set_threads(cores)
     return {"value": sub.shape[0] * args.cpu_steps / dt, "unit": "chain-steps/s",
-            "cores": cores, "kind": "oracle",
+            "cores": cores, "kind": "oracle", "cpu_model": host["model"],
+            "host_logical_cpus": host["logical_cpus"],
             "sample": f"{sub.shape[0]} chains x {args.beads} beads x {args.cpu_steps} mode "
                       f"steps (FP64 plain C, OpenMP over chains), {dt:.1f} s",
             "single_core": {"value": 32 * 50 / dt1, "unit": "chain-steps/s",
@@ -246,6 +265,63 @@ def shear_workload(args):
     print(json.dumps({"workload": f"shear: {B} chains x {M} bp, dtau = {dtau:g}, "
                                   f"{args.shear_steps} steps, samples every {se}",
                       "precision": prec, "results": res}))
+
+
+def stats_workload(args):
+    """Statistics of the reduced-precision paths against the FP64 plain form
+    on the GPU at the batched configurations (1024 x 128 bp at dtau 50,
+    4096 x 256 and 1024 x 512 bp at dtau 100; random orientation plus
+    jitter, seed 1), --stats-steps steps each (default 1e5), observables
+    every 100 steps, paired runs on identical Philox streams.  Per
+    observable: the relative difference of its time and ensemble average
+    from FP64 (the target is 2 %), and the centre-of-mass diffusion
+    coefficient against D = T*/M (Sec. VII.B)."""
+    import numpy as np
+    import torch
+    from paper_1411_3487_amd import Context, inputs, NU_DSDNA, T_STAR_DSDNA
+    torch.cuda.set_device(0)
+    b = 1.0 / (1.0 - 2.0 * NU_DSDNA)
+    n, se = args.stats_steps, 100
+    confs = [(1024, 128, 50.0), (4096, 256, 100.0), (1024, 512, 100.0)]
+    out = []
+    for B, M, dtau in confs:
+        pos = inputs.straight_chains(B, M, b, seed=1, random_orientation=True)
+        acc, wall = {}, {}
+        for p in ("fp64", "fp32", "bf16x3"):
+            t0 = time.perf_counter()
+            with Context(pos, seed=1, precision=p) as ctx:
+                ctx.set_params([M], [dtau], T_star=T_STAR_DSDNA, nu=NU_DSDNA, sample_every=se,
+                               use_graphs=True, autotune=p != "fp64")
+                steps_with_progress(ctx, n, f"{B}x{M} {p}", chunk=20000)
+                acc[p] = ctx.accumulators()[0]
+            wall[p] = time.perf_counter() - t0
+            print(f"# {B}x{M} {p}: {n} steps in {wall[p]:.1f} s", file=sys.stderr, flush=True)
+        ns = acc["fp64"]["n_samples"]
+        t = dtau * se * np.arange(1, ns + 1)
+        row = {"chains": B, "beads": M, "dtau": dtau, "steps": n, "samples": int(ns),
+               "seconds": wall}
+        for p in ("fp64", "fp32", "bf16x3"):
+            a = acc[p]
+            D = a["msd_cm"] / B / (6.0 * t.sum())
+            row[p] = {"bond": a["bond"] / ns / B, "bond2": a["bond2"] / ns / B,
+                      "L2": a["L2"] / ns / B, "dmid2": a["dmid2"] / ns / B,
+                      "D_over_TstarM": D / (T_STAR_DSDNA / M)}
+        ref = acc["fp64"]
+        for p in ("fp32", "bf16x3"):
+            a = acc[p]
+            rel = {k: a[k] / ref[k] - 1 for k in ("bond", "bond2", "L2", "dmid2", "msd_cm")}
+            rel["end_to_end_rms"] = np.sqrt(a["L2"] / ref["L2"]) - 1
+            mrel = a["modes"][1:] / ref["modes"][1:] - 1
+            rel["modes_max_abs"] = float(np.abs(mrel).max())
+            rel["modes_p1_to_p5"] = [float(x) for x in mrel[:5]]
+            rel["within_2pct"] = bool(all(abs(v) < 0.02 for k, v in rel.items()
+                                          if isinstance(v, float)))
+            row[f"{p}_rel_diff_vs_fp64"] = rel
+        out.append(row)
+        print(f"# {B}x{M}: {row['bf16x3_rel_diff_vs_fp64']}", file=sys.stderr, flush=True)
+    print(json.dumps({"workload": f"reduced precision vs FP64 GPU statistics, {n} steps, "
+                                  f"observables every {se} steps",
+                      "results": out}))
 
 
 def profile_launches(args):
@@ -384,7 +460,7 @@ def dtmax_workload(args):
     Carlo first, and every dynamics run starts from that state."""
     import numpy as np
     import torch
-    from paper_1411_3487_amd import Context, inputs, NU_DSDNA, T_STAR_DSDNA
+    from paper_1411_3487_amd import Context, dtmax, inputs, NU_DSDNA, T_STAR_DSDNA
     torch.cuda.set_device(0)
     b = 1.0 / (1.0 - 2.0 * NU_DSDNA)
     # time steps bracketing the paper's Table 1 (50, 100, 100, 100 at N = 63,
@@ -434,11 +510,11 @@ def dtmax_workload(args):
             ctx.close()
             ratio = {k: d[k] / d["n_samples"] / ref[k] for k in keys}
             rows.append({"dtau": dt, "steps": 2 * n, "ratios": ratio,
-                         "within_5pct": all(abs(r - 1) < 0.05 for r in ratio.values())})
+                         "within_5pct": dtmax.q0_passes(ratio.values())})
             print(f"# M={M} dtau={dt}: {ratio}", file=sys.stderr, flush=True)
-        ok = [r["dtau"] for r in rows if r["within_5pct"]]
         out.append({"M": M, "N": M - 1, "mc_reference": ref, "runs": rows,
-                    "dtau_max_from_Q0": max(ok) if ok else None})
+                    "dtau_max_from_Q0": dtmax.contiguous_dtau_max(
+                        [r["dtau"] for r in rows], [r["within_5pct"] for r in rows])})
     print(json.dumps({"workload": f"dtau_max from equilibrium values, {B} chains per length, "
                                   f"{args.precision} mode dynamics vs FP64 Monte Carlo",
                       "results": out}))
@@ -455,7 +531,7 @@ def dtmax_t_workload(args):
     decayed below 5 % of their start are left out (noise)."""
     import numpy as np
     import torch
-    from paper_1411_3487_amd import Context, inputs, NU_DSDNA, T_STAR_DSDNA
+    from paper_1411_3487_amd import Context, dtmax, inputs, NU_DSDNA, T_STAR_DSDNA
     torch.cuda.set_device(0)
     b = 1.0 / (1.0 - 2.0 * NU_DSDNA)
     B, K = 1024, 14
@@ -463,7 +539,7 @@ def dtmax_t_workload(args):
     #     Monte Carlo burn-in sweeps)
     plan = {64: ([0.1, 1, 10, 20, 50, 100], 100.0, 2.0e6, [100, 1e3, 1e4, 1e5], 3000),
             128: ([1, 10, 50, 100, 200], 1000.0, 2.0e7, [1e3, 1e4, 1e5, 1e6], 8000),
-            256: ([10, 100, 200, 500], 1.0e4, 1.0e8, [1e4, 1e5, 1e6, 1e7], 20000),
+            256: ([1, 10, 100, 200, 500], 1.0e4, 1.0e8, [1e4, 1e5, 1e6, 1e7], 20000),
             512: ([10, 100, 200, 500], 1.0e5, 5.0e8, [1e5, 1e6, 1e7, 1e8], 20000)}
     lengths = [int(x) for x in args.dtmax_lengths.split(",") if x]
     if any(M not in plan for M in lengths):
@@ -502,41 +578,17 @@ def dtmax_t_workload(args):
             print(f"# M={M} dtau={dt}: {n} steps, {time.perf_counter() - t0:.0f} s",
                   file=sys.stderr, flush=True)
         ref = curves[dts[0]]
-
-        def decay(q, i, t):
-            # d ln Q / d tau at lag t by a central difference on the lag grid
-            j = int(np.argmin(np.abs(lags - t)))
-            j = min(max(j, 1), K - 2)
-            lo, hi = q[j - 1, i], q[j + 1, i]
-            if lo <= 0 or hi <= 0:
-                return None, lags[j]
-            return (np.log(hi) - np.log(lo)) / (lags[j + 1] - lags[j - 1]), lags[j]
         rows = []
         for dt in dts[1:]:
-            ratios, ok = {}, True
-            for i, name in enumerate(names):
-                for t in times:
-                    j = int(np.argmin(np.abs(lags - t)))
-                    if i < 2 and (ref[j, i] < 0.05 * ref[0, i]):
-                        continue                       # decayed: noise only
-                    qa, tt = decay(curves[dt], i, t)
-                    qb, _ = decay(ref, i, t)
-                    if qa is None or qb is None or qb == 0:
-                        continue
-                    r = float(qa / qb)
-                    ratios[f"{name}@{tt:g}"] = r
-                    ok = ok and abs(r - 1) <= 0.10
-            rows.append({"dtau": dt, "ratios": ratios, "within_10pct": bool(ok)})
+            ratios, ok = dtmax.qt_ratios(curves[dt], ref, lags, times, names)
+            rows.append({"dtau": dt, "ratios": ratios, "within_10pct": ok})
             print(f"# M={M} dtau={dt}: ok={ok} {ratios}", file=sys.stderr, flush=True)
-        passed = []
-        for r in rows:
-            if not r["within_10pct"]:
-                break
-            passed.append(r["dtau"])
+        best = dtmax.contiguous_dtau_max([r["dtau"] for r in rows],
+                                         [r["within_10pct"] for r in rows])
         out.append({"M": M, "N": M - 1, "dtau_min": dts[0], "runs": rows,
                     "lags_tau": lags.tolist(),
                     "Q_ref": {n: ref[:, i].tolist() for i, n in enumerate(names)},
-                    "dtau_max_from_Qt": passed[-1] if passed else dts[0]})
+                    "dtau_max_from_Qt": best})
     print(json.dumps({"workload": f"dtau_max from time correlations, {B} chains per length, "
                                   f"{args.precision} mode dynamics",
                       "results": out}))
@@ -673,6 +725,8 @@ def main():
         return euler_workload(args)
     if args.workload == "dtmax" and args.gpus == 1:
         return dtmax_workload(args)
+    if args.workload == "stats" and args.gpus == 1:
+        return stats_workload(args)
     if args.profile_launches:
         return profile_launches(args)
     if args.workload != "modes" and args.gpus == 1:
@@ -703,39 +757,50 @@ def main():
     b = 1.0 / (1.0 - 2.0 * NU_DSDNA)
     pos = inputs.straight_chains(B, M, b, seed=1, random_orientation=True)
 
-    # ---- mixed precision: the measured path
+    # ---- mixed precision: the measured path.  Warm-up and timed steps are
+    # rounded up to whole sampling blocks, so the timed region starts on a
+    # block boundary and is made of replayed sampling blocks, each with its
+    # observable sample, whatever --steps and --warmup say.
+    se = args.sample_every
+    blocks = lambda n: -(-n // se) * se if se > 0 else n
+    warmup, steps = blocks(args.warmup), blocks(max(args.steps, 1))
     ctx = Context(pos, seed=1, precision=args.precision, stream=stream)
     ctx.set_params([M], [args.dtau], T_star=T_STAR_DSDNA, nu=NU_DSDNA,
-                   sample_every=args.sample_every, use_graphs=not args.no_graphs,
+                   sample_every=se, use_graphs=not args.no_graphs,
                    autotune=not args.no_autotune, table_mode=args.table_mode)
     tiling, report = ctx.tiling()[0], ctx.tuning_report()
     shape = "split" if tiling["split"] else ("resident" if tiling["resident"] else "streamed")
-    ctx.step_modes(args.warmup)
+    ctx.step_modes(warmup)
     torch.cuda.synchronize()
+    n0 = ctx.accumulators()[0]["n_samples"]
+    s0 = ctx.step
     t0 = time.perf_counter()
-    ctx.step_modes(args.steps)
+    ctx.step_modes(steps)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    samples_timed = int(ctx.accumulators()[0]["n_samples"] - n0)
+    graphs_used = (not args.no_graphs) and se > 0 and s0 % se == 0 and steps >= se
     obs = ctx.chain_observables()
     finite = bool(np.all(np.isfinite(obs)))
     # dominant kernel alone, in the launch shape of the timed loop: one fused
     # launch covers the steps between two observable samples
     ctx.set_params([M], [args.dtau], T_star=T_STAR_DSDNA, nu=NU_DSDNA, sample_every=0,
                    tiles_per_wg=int(tiling["tpw"]), table_mode=shape)
-    k_launch = args.sample_every if args.sample_every > 0 else 100
+    k_launch = se if se > 0 else 100
     kern = sorted(time_steps(ctx, torch, k_launch, stream) for _ in range(9))[4]
     ctx.close()
 
-    # ---- FP64 plain form on the same GPU and workload
+    # ---- FP64 plain form on the same GPU and workload, over the same kind
+    # of window: whole sampling blocks from a block boundary
     c64 = Context(pos, seed=1, precision="fp64", stream=stream)
-    c64.set_params([M], [args.dtau], T_star=T_STAR_DSDNA, nu=NU_DSDNA,
-                   sample_every=args.sample_every)
-    c64.step_modes(20)
-    t64 = time_steps(c64, torch, args.fp64_steps, stream)
+    c64.set_params([M], [args.dtau], T_star=T_STAR_DSDNA, nu=NU_DSDNA, sample_every=se)
+    fp64_steps = blocks(args.fp64_steps)
+    c64.step_modes(blocks(20))
+    t64 = time_steps(c64, torch, fp64_steps, stream)
     c64.close()
 
-    chain_steps = B * args.steps / wall
-    fp64_rate = B * args.fp64_steps / t64
+    chain_steps = B * steps / wall
+    fp64_rate = B * fp64_steps / t64
     exec_flops = executed_flops(args.precision, M, int(tiling["JC"]))  # per chain-step
     achieved = exec_flops * B * k_launch / kern
     traffic = measured_traffic(args.precision, B, M)
@@ -746,19 +811,25 @@ def main():
         "value": chain_steps,
         "unit": "chain-steps/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": wall / args.steps * 1e3,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": wall / steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": {"bf16x3": "bf16x3-f32acc", "fp32": "f32"}[args.precision],
         "data": "synthetic",
         "config": {"workload": f"{B} chains x {M} bp dsDNA (nu=0.35, T*=0.034), "
-                               f"dtau={args.dtau:g} (15.9 ps), observables every "
-                               f"{args.sample_every} steps",
+                               f"dtau={args.dtau:g} ({dt_ps:.3g} ps), observables every "
+                               f"{se} steps",
                    "chains": B, "beads": M, "parallelism": "1 GPU, chains data-parallel",
-                   "launch": {"graphs": not args.no_graphs, "autotune": not args.no_autotune,
+                   "timed_region": {"steps_requested": args.steps, "warmup_requested": args.warmup,
+                                    "steps": steps, "warmup": warmup,
+                                    "samples_in_timed_region": samples_timed,
+                                    "graph_replays": steps // se if graphs_used else 0,
+                                    "fp64_steps": fp64_steps,
+                                    "fp64_samples": fp64_steps // se if se > 0 else 0},
+                   "launch": {"graphs": graphs_used, "autotune": not args.no_autotune,
                               "tables": shape, "tiles_per_wg": int(tiling["tpw"]),
                               "coupling_row_tiles": int(tiling["JC"]), "row_tiles": int(tiling["RT"]),
                               "tuning_report": report.strip().splitlines()}},

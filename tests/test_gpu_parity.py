@@ -62,6 +62,28 @@ def test_fp64_mode_steps_match_oracle(B, M, dtau, n):
     assert np.abs(modes - Rref).max() <= 1e-9 * np.abs(Rref).max()
 
 
+@pytest.mark.parametrize("B,M,dtau,ids", [(1024, 128, 50.0, [0, 1, 2, 3, 511, 512, 1000, 1023]),
+                                          (4096, 256, 100.0, [0, 1337, 2048, 4095]),
+                                          (1024, 512, 100.0, [5, 1023])])
+def test_fp64_thousand_steps_on_the_batched_configurations(B, M, dtau, ids):
+    """1e3 FP64 mode steps of the whole batched ensemble (1024 x 128 bp at
+    dtau 50; 4096 x 256 and 1024 x 512 bp at dtau 100; random orientation,
+    seed 1) on the GPU; the oracle advances the sampled chains with their
+    ensemble chain indices (same Philox streams) and must agree to 1e-10 of
+    the contour length."""
+    n = 1000
+    pos = inputs.straight_chains(B, M, B_FAC, seed=1, random_orientation=True)
+    with Context(pos, seed=1, precision="fp64") as ctx:
+        ctx.set_params([M], [dtau], T_star=TS, nu=NU)
+        ctx.step_modes(n)
+        got = ctx.positions()
+    ref = oracle_positions(pos[ids], dtau, n, seed=1, ids=ids)
+    err = rel_pos_err(got[ids], ref)
+    print(f"B={B} M={M} dtau={dtau} n={n} chains {ids}: rel err {err:.3e}")
+    assert err < FP64_TOL
+    assert np.all(np.isfinite(got))
+
+
 def test_fp64_uneven_lengths_in_one_context():
     beads = [64, 17, 2, 64, 100, 3, 17]
     chains = [inputs.straight_chains(1, m, B_FAC, seed=10 + i)[0] for i, m in enumerate(beads)]
