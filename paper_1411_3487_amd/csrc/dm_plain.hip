@@ -94,6 +94,17 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const double *__restrict_
 // is.
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 
+// Workgroups of a launch are dispatched round-robin over the GPU's 8 XCDs
+// (workgroup w to XCD w % 8), each with its own L2.  This maps the
+// dispatch index w of n workgroups to a logical index such that every XCD
+// takes one contiguous range of logical indices (a bijection on [0, n)).
+__device__ __forceinline__ int xcd_local_index(int w, int n)
+{
+    constexpr int kXcd = 8;
+    const int q = n / kXcd, r = n % kXcd, x = w % kXcd, s = w / kXcd;
+    return x < r ? x * (q + 1) + s : r * (q + 1) + (x - r) * q + s;
+}
+
 template <int BN>
 __global__ __launch_bounds__(256) void gemm_f64_pipe_kernel(const double *__restrict__ A,
                                                             const double *__restrict__ X,
@@ -106,8 +117,13 @@ __global__ __launch_bounds__(256) void gemm_f64_pipe_kernel(const double *__rest
     __shared__ double Xs[2][BN][kGemmBK + 1];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wi = wave >> 1, wj = wave & 1;
-    const int i0 = blockIdx.x * kGemmBM;
-    const int c0 = blockIdx.y * BN;
+    // one-dimensional grid, row tiles fastest in the XCD-local order: the
+    // row tiles that read the same column block of X run on one XCD and
+    // share its L2, so each X block crosses HBM about once
+    const int nrt = (M + kGemmBM - 1) / kGemmBM;
+    const int L = xcd_local_index((int)blockIdx.x, (int)gridDim.x);
+    const int i0 = (L % nrt) * kGemmBM;
+    const int c0 = (L / nrt) * BN;
     // each thread moves 4 consecutive k of one row of A and (lr < BN) of one
     // column of X
     const int lr = tid >> 2, lk = (tid & 3) * 4;
@@ -242,14 +258,63 @@ __global__ __launch_bounds__(256) void mode_update_f64_kernel(
         if (p >= M) break;
         const double ry = Rc[M + p];
         const double e = E[p], w = W[p], cc = C[p];
+        double v[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            double v = e * Rc[a * M + p] + w * z[a][j];
-            if (nonlinear && p > 0) v += cc * dHc[a * M + p];
-            Rc[a * M + p] = v;
+            v[a] = e * Rc[a * M + p] + w * z[a][j];
+            if (nonlinear && p > 0) v[a] += cc * dHc[a * M + p];
         }
-        Rc[p] += gdt * e * ry;
+        v[0] += gdt * e * ry;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) Rc[a * M + p] = v[a];
     }
+}
+
+// The same update for even M with 16-byte accesses: one thread per (chain,
+// mode pair h), modes 2h and 2h+1 of all three components, so the lanes of a
+// wavefront read and write 1 KB contiguous runs of every row and the shear
+// term is folded into the one store.  The pair's normals are the two of its
+// Box-Muller pair in Philox block h/2 (the neighbouring thread draws the same
+// block for the other pair), the same numbers as above.
+__global__ __launch_bounds__(256) void mode_update_f64_pair_kernel(
+    double *__restrict__ R, const double *__restrict__ dH, const double *__restrict__ E,
+    const double *__restrict__ C, const double *__restrict__ W,
+    const int32_t *__restrict__ ids, int M, int nch, uint64_t seed,
+    const int64_t *__restrict__ step_dev, int64_t step_off, double gdt, int nonlinear)
+{
+    const int H = M / 2;
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (size_t)nch * H) return;
+    const int c = (int)(idx / H), h = (int)(idx % H);
+    const int64_t k = (step_dev ? *step_dev : 0) + step_off;
+    const uint32_t chain = (uint32_t)ids[c];
+    const f64x2 e = reinterpret_cast<const f64x2 *>(E)[h];
+    const f64x2 w = reinterpret_cast<const f64x2 *>(W)[h];
+    const f64x2 cc = reinterpret_cast<const f64x2 *>(C)[h];
+    f64x2 *Rc = reinterpret_cast<f64x2 *>(R + (size_t)c * 3 * M) + h;
+    const f64x2 *dHc = reinterpret_cast<const f64x2 *>(dH + (size_t)c * 3 * M) + h;
+    f64x2 r[3], d[3], v[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        r[a] = Rc[a * H];
+        d[a] = nonlinear ? dHc[a * H] : f64x2{0.0, 0.0};
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        double z[2];
+        normal_pair_f64(noise_bits(seed, (uint32_t)(h >> 1), chain, k, (uint32_t)a, kTagMode),
+                        h & 1, z);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            double x = e[j] * r[a][j] + w[j] * z[j];
+            if (nonlinear && 2 * h + j > 0) x += cc[j] * d[a][j];
+            v[a][j] = x;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) v[0][j] += gdt * e[j] * r[1][j];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) Rc[a * H] = v[a];
 }
 
 // --------------------------------------------------------------------------
@@ -1035,11 +1100,12 @@ hipError_t launch_gemm_f64(const double *A, const double *X, double *Y, int M, i
         // narrower column tiles while 64 x 64 tiles would not give every CU
         // of the GPU two workgroups
         if (grid.x * grid.y < 512) {
-            grid.y = (ncol + 31) / 32;
-            hipLaunchKernelGGL(gemm_f64_pipe_kernel<32>, grid, dim3(256), 0, st, A, X, Y, M,
+            const dim3 g1(grid.x * ((ncol + 31) / 32));
+            hipLaunchKernelGGL(gemm_f64_pipe_kernel<32>, g1, dim3(256), 0, st, A, X, Y, M,
                                ncol);
         } else {
-            hipLaunchKernelGGL(gemm_f64_pipe_kernel<64>, grid, dim3(256), 0, st, A, X, Y, M,
+            const dim3 g1(grid.x * grid.y);
+            hipLaunchKernelGGL(gemm_f64_pipe_kernel<64>, g1, dim3(256), 0, st, A, X, Y, M,
                                ncol);
         }
     } else {
@@ -1063,6 +1129,14 @@ hipError_t launch_mode_update_f64(double *R, const double *dH, const double *E, 
                                   uint64_t seed, const int64_t *step_dev, int64_t step_off,
                                   double gdt, int nonlinear, hipStream_t st)
 {
+    if (M % 2 == 0) {
+        const size_t n = (size_t)nch * (M / 2);
+        if (n == 0) return hipSuccess;
+        hipLaunchKernelGGL(mode_update_f64_pair_kernel, dim3(blocks_for(n, 256)), dim3(256), 0,
+                           st, R, dH, E, C, W, ids, M, nch, seed, step_dev, step_off, gdt,
+                           nonlinear);
+        return hipGetLastError();
+    }
     const size_t n = (size_t)nch * ((M + 3) / 4);
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(mode_update_f64_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, R,

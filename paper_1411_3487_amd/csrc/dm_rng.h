@@ -71,21 +71,24 @@ __host__ __device__ __forceinline__ Block4 noise_bits(uint64_t seed, uint32_t bl
                          (uint32_t)seed, (uint32_t)(seed >> 32));
 }
 
-// Four N(0,1) in FP64: uniforms (x + 1/2) 2^-32, two Box-Muller pairs.
-__host__ __device__ __forceinline__ void normals4_f64(const Block4 &b, double z[4])
+// Box-Muller pair `second` (0: words 0, 1; 1: words 2, 3) of a block in
+// FP64: uniforms (x + 1/2) 2^-32, z = sqrt(-2 ln u_a) (cos, sin)(2 pi u_b).
+__host__ __device__ __forceinline__ void normal_pair_f64(const Block4 &b, int second, double z[2])
 {
     const double scale = 2.3283064365386962890625e-10;  // 2^-32
     const double two_pi = 6.283185307179586476925286766559;
-    const double u0 = ((double)b.v[0] + 0.5) * scale;
-    const double u1 = ((double)b.v[1] + 0.5) * scale;
-    const double u2 = ((double)b.v[2] + 0.5) * scale;
-    const double u3 = ((double)b.v[3] + 0.5) * scale;
-    const double ra = sqrt(-2.0 * log(u0));
-    const double rb = sqrt(-2.0 * log(u2));
-    z[0] = ra * cos(two_pi * u1);
-    z[1] = ra * sin(two_pi * u1);
-    z[2] = rb * cos(two_pi * u3);
-    z[3] = rb * sin(two_pi * u3);
+    const double ua = ((double)b.v[2 * second] + 0.5) * scale;
+    const double ub = ((double)b.v[2 * second + 1] + 0.5) * scale;
+    const double ra = sqrt(-2.0 * log(ua));
+    z[0] = ra * cos(two_pi * ub);
+    z[1] = ra * sin(two_pi * ub);
+}
+
+// Four N(0,1) in FP64: the block's two Box-Muller pairs.
+__host__ __device__ __forceinline__ void normals4_f64(const Block4 &b, double z[4])
+{
+    normal_pair_f64(b, 0, z);
+    normal_pair_f64(b, 1, z + 2);
 }
 
 #if defined(__HIP_DEVICE_COMPILE__) || defined(__HIPCC__)
