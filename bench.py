@@ -28,7 +28,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--workload", default="modes",
                     choices=["modes", "uneven", "shear", "mc", "dtmax", "dtmax_t", "wlc", "euler",
-                             "stats"],
+                             "stats", "fp64"],
                     help="modes: 4096 x 256 bp (the headline line); uneven: 8192 chains of "
                          "64..512 bp in one launch; shear: 2048 x 256 bp under simple shear "
                          "at Wi = 1, 10, 100 (tumbling and extension, FP32 vs FP64); mc: "
@@ -322,6 +322,30 @@ def stats_workload(args):
     print(json.dumps({"workload": f"reduced precision vs FP64 GPU statistics, {n} steps, "
                                   f"observables every {se} steps",
                       "results": out}))
+
+
+def fp64_workload(args):
+    """The FP64 plain form alone on the default workload (--chains x --beads,
+    --dtau), --steps timed steps with HIP events after --warmup: the
+    denominator of the mixed-precision speed-up, for profiling its kernels."""
+    import numpy as np
+    import torch
+    from paper_1411_3487_amd import Context, inputs, NU_DSDNA, T_STAR_DSDNA
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    b = 1.0 / (1.0 - 2.0 * NU_DSDNA)
+    B, M = args.chains, args.beads
+    pos = inputs.straight_chains(B, M, b, seed=1, random_orientation=True)
+    with Context(pos, seed=1, precision="fp64", stream=stream) as c64:
+        c64.set_params([M], [args.dtau], T_star=T_STAR_DSDNA, nu=NU_DSDNA, sample_every=0)
+        c64.step_modes(args.warmup)
+        sec = time_steps(c64, torch, args.steps, stream)
+        finite = bool(np.all(np.isfinite(c64.modes())))
+    print(json.dumps({"metric": "chain-steps/s, FP64 plain form", "value": B * args.steps / sec,
+                      "unit": "chain-steps/s", "us_per_step": sec / args.steps * 1e6,
+                      "state_finite": finite,
+                      "config": {"workload": f"{B} chains x {M} bp, dtau {args.dtau:g}, "
+                                             f"{args.steps} steps, no observables"}}))
 
 
 def profile_launches(args):
@@ -727,6 +751,8 @@ def main():
         return dtmax_workload(args)
     if args.workload == "stats" and args.gpus == 1:
         return stats_workload(args)
+    if args.workload == "fp64" and args.gpus == 1:
+        return fp64_workload(args)
     if args.profile_launches:
         return profile_launches(args)
     if args.workload != "modes" and args.gpus == 1:
