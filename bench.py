@@ -124,10 +124,13 @@ def host_cpu():
     return {"model": model, "logical_cpus": os.cpu_count()}
 
 
-def cpu_baseline(args, pos, nu, ts):
+def cpu_baseline(args, nu, ts):
+    """The oracle on a sample of the same workload: the first --cpu-sample
+    chains of the library's initial state (the oracle's own generator of the
+    same recipe, seed 1), --cpu-steps mode steps."""
     import numpy as np
     import oracle
-    sub = pos[: args.cpu_sample]
+    sub = oracle.config_chains(args.beads, args.cpu_sample, nu, seed=1)
     R = oracle.modes_from_positions(sub)
     oracle.step_modes(R[:2], nu, ts, args.dtau, 1, seed=1)  # load + warm
     t0 = time.perf_counter()
@@ -780,8 +783,9 @@ def main():
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
     B, M = args.chains, args.beads
-    b = 1.0 / (1.0 - 2.0 * NU_DSDNA)
-    pos = inputs.straight_chains(B, M, b, seed=1, random_orientation=True)
+    # the library's own initial state (straight chains, Philox-uniform
+    # directions, jitter 0.01 a; seed 1), built at set_params
+    beads = [M] * B
 
     # ---- mixed precision: the measured path.  Warm-up and timed steps are
     # rounded up to whole sampling blocks, so the timed region starts on a
@@ -790,7 +794,7 @@ def main():
     se = args.sample_every
     blocks = lambda n: -(-n // se) * se if se > 0 else n
     warmup, steps = blocks(args.warmup), blocks(max(args.steps, 1))
-    ctx = Context(pos, seed=1, precision=args.precision, stream=stream)
+    ctx = Context(None, seed=1, precision=args.precision, stream=stream, beads=beads)
     ctx.set_params([M], [args.dtau], T_star=T_STAR_DSDNA, nu=NU_DSDNA,
                    sample_every=se, use_graphs=not args.no_graphs,
                    autotune=not args.no_autotune, table_mode=args.table_mode)
@@ -818,7 +822,7 @@ def main():
 
     # ---- FP64 plain form on the same GPU and workload, over the same kind
     # of window: whole sampling blocks from a block boundary
-    c64 = Context(pos, seed=1, precision="fp64", stream=stream)
+    c64 = Context(None, seed=1, precision="fp64", stream=stream, beads=beads)
     c64.set_params([M], [args.dtau], T_star=T_STAR_DSDNA, nu=NU_DSDNA, sample_every=se)
     fp64_steps = blocks(args.fp64_steps)
     c64.step_modes(blocks(20))
@@ -844,7 +848,7 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": {"bf16x3": "bf16x3-f32acc", "fp32": "f32"}[args.precision],
-        "data": "synthetic",
+        "data": "synthetic: straight chains, Philox-uniform directions, jitter 0.01 a (seed 1)",
         "config": {"workload": f"{B} chains x {M} bp dsDNA (nu=0.35, T*=0.034), "
                                f"dtau={args.dtau:g} ({dt_ps:.3g} ps), observables every "
                                f"{se} steps",
@@ -878,7 +882,7 @@ def main():
                             "this_gpu_per_chain": per_hour(chain_steps / B),
                             "this_gpu_all_chains": per_hour(chain_steps)}
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args, pos, NU_DSDNA, T_STAR_DSDNA)
+        out["cpu_baseline"] = cpu_baseline(args, NU_DSDNA, T_STAR_DSDNA)
         out["paper_context"]["oracle_one_core"] = per_hour(
             out["cpu_baseline"]["single_core"]["value"])
     print(json.dumps(out))

@@ -38,7 +38,9 @@
  *    Box-Muller pairs, normal j of the block belongs to index 4*(index/4)+j.
  *    tag 0 = mode step (index = mode p), 1 = Euler step (index = bead n),
  *    2 = Monte Carlo sweep (index = mode p, see dm_step_mc),
- *    3 = inextensible limit (index = bead n, see dm_step_wlc).
+ *    3 = inextensible limit (index = bead n, see dm_step_wlc),
+ *    4 and 5 = initial state of a context created without positions
+ *    (see dm_init_chains).
  *    Results are therefore independent of how chains are batched.
  */
 #ifndef DNAMODES_H
@@ -195,7 +197,14 @@ typedef struct {
 /* Create a context for n_chains chains; beads[c] >= 2 is the number of beads
    of chain c (host array, at most 2048).  pos0 (host, SoA, sum_c 3*beads[c] doubles, in
    units of d) is the initial conformation; it is transformed to mode
-   amplitudes in FP64, Eq. (c1).  Chains are grouped into buckets of equal
+   amplitudes in FP64, Eq. (c1).  pos0 may be NULL: the first dm_set_params
+   then builds the initial state of the batched workloads (the paper
+   prescribes none): chain c straight with bond length b = 1/(1 - 2 nu) along
+   a direction uniform on the unit sphere (Philox tag 5, index 0, step 0:
+   cos(theta) = 2 U0 - 1, phi = 2 pi U1 from words 0 and 1), every coordinate
+   jittered by 0.01 b times a normal (tag 4, index bead n, component a, step
+   0); until then every call that reads or advances the state returns
+   DM_ESTATE (dm_load_state supplies a state instead).  Chains are grouped into buckets of equal
    length internally; chain c keeps Philox chain index c.  precision is one
    of DM_FP64, DM_FP32, DM_BF16X3 (the fused paths need an even number of
    beads, at most 512).  hip_stream is a hipStream_t (NULL = the null stream).

@@ -71,6 +71,7 @@ def _load():
         "orc_mc_sweeps": (None, [_i, _i, _p, _p, _d, _d, _d, _u64, _i64, _i64, _p]),
         "orc_step_wlc": (None, [_i, _i, _p, _p, _d, _d, _i, _d, _u64, _i64, _i64]),
         "orc_chain_observables": (None, [_i, _p, _p]),
+        "orc_config_chains": (None, [_i, _i, _p, _d, _u64, _p]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -236,6 +237,18 @@ def mc_sweeps(R, nu, T_star, scale, n_sweeps, seed=0, step0=0, chain_ids=None):
 def energy(pos, nu) -> float:
     pos = _f64(pos)
     return _load().orc_energy(pos.shape[-1], nu, _ptr(pos))
+
+
+def config_chains(M: int, n_chains: int, nu: float, seed: int, chain_ids=None) -> np.ndarray:
+    """Initial state of the batched workloads, (B, 3, M): straight chains of
+    bond length b = 1/(1 - 2 nu) along a direction uniform on the sphere,
+    jittered by 0.01 b per coordinate (Philox tags 5 and 4, step 0)."""
+    lib = _load()
+    ids = np.arange(n_chains, dtype=np.uint32) if chain_ids is None else \
+        np.ascontiguousarray(chain_ids, dtype=np.uint32)
+    out = np.zeros((len(ids), 3, M))
+    lib.orc_config_chains(M, len(ids), _ptr(ids), 1.0 / (1.0 - 2.0 * nu), seed, _ptr(out))
+    return out
 
 
 OBS_NAMES = ["bond_mean", "L2", "Lx", "Ly", "Lz", "cmx", "cmy", "cmz",

@@ -120,6 +120,35 @@ double orc_normal(uint64_t seed, uint32_t index, uint32_t chain, int64_t step,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Initial state of the batched workloads (the paper prescribes none): each */
+/* chain straight, its beads b apart along a direction e uniform on the     */
+/* unit sphere, every coordinate jittered by 0.01 b times a standard normal.*/
+/* Philox, step 0: tag 5 block (0, chain, 0, comp 0) gives the direction    */
+/* from its first two uniforms, cos(theta) = 2 U0 - 1, phi = 2 pi U1;       */
+/* tag 4 gives the jitter, normal index = bead n, component a.              */
+/* ------------------------------------------------------------------------ */
+void orc_config_chains(int M, int n_chains, const uint32_t *chain_id, double b,
+                       uint64_t seed, double *pos)
+{
+    const double two_m32 = 1.0 / 4294967296.0;
+    const double two_pi = 6.283185307179586476925286766559;
+    for (int c = 0; c < n_chains; ++c) {
+        uint32_t ctr[4] = {0u, chain_id[c], 0u, 5u};
+        uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+        uint32_t x[4];
+        orc_philox4x32_10(ctr, key, x);
+        double u0 = ((double)x[0] + 0.5) * two_m32, u1 = ((double)x[1] + 0.5) * two_m32;
+        double ct = 2.0 * u0 - 1.0, st = sqrt(1.0 - ct * ct), ph = two_pi * u1;
+        double e[3] = {st * cos(ph), st * sin(ph), ct};
+        double *r = pos + (size_t)c * 3 * M;
+        for (int a = 0; a < 3; ++a)
+            for (int n = 0; n < M; ++n)
+                r[a * M + n] = n * b * e[a] +
+                               0.01 * b * orc_normal(seed, (uint32_t)n, chain_id[c], 0, (uint32_t)a, 4u);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
 /* Model parameters, Sec. 2 (Eqs. a2, a3) and Sec. 7b (Eq. g2).             */
 /* ------------------------------------------------------------------------ */
 void orc_reduced_params(double lambda, double kappa, double kT, double a,

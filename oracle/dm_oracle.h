@@ -40,5 +40,7 @@ void orc_mc_sweeps(int M, int n_chains, const uint32_t *chain_id, double *R,
                    double nu, double T_star, double scale, uint64_t seed,
                    int64_t step0, int64_t n_sweeps, int64_t *accepted);
 void orc_chain_observables(int M, const double *pos, double *out);
+void orc_config_chains(int M, int n_chains, const uint32_t *chain_id, double b,
+                       uint64_t seed, double *pos);
 
 #endif

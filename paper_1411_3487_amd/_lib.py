@@ -66,7 +66,8 @@ EXPORTS = ["dm_init_chains", "dm_set_params", "dm_step_modes", "dm_step_euler", 
            "dm_step_wlc",
            "dm_observables", "dm_observables_size", "dm_get_positions", "dm_get_modes",
            "dm_save_state", "dm_load_state", "dm_get_step", "dm_get_tiling",
-           "dm_tuning_report", "dm_coarse_grain", "dm_coarse_grain_time", "dm_sync", "dm_destroy", "dm_last_error"]
+           "dm_tuning_report", "dm_coarse_grain", "dm_coarse_grain_time", "dm_sync", "dm_destroy",
+           "dm_last_error"]
 
 _lib = None
 
@@ -139,18 +140,24 @@ class Context:
     """One dm_ctx: a batch of chains on the current HIP device.
 
     pos0 is a list of (3, M_c) arrays, or a (B, 3, M) array for equal lengths,
-    in units of d.  stream is a torch.cuda.Stream (or None for the null stream).
+    in units of d; or None with ``beads`` (chain lengths): then the library
+    builds its own initial state at the first set_params (see dm_init_chains).  stream is a torch.cuda.Stream (or None for the null stream).
     """
 
-    def __init__(self, pos0, seed: int = 0, precision="fp64", stream=None):
+    def __init__(self, pos0, seed: int = 0, precision="fp64", stream=None, beads=None):
         self.lib = load()
-        if isinstance(pos0, np.ndarray) and pos0.ndim == 3:
-            chains = [pos0[i] for i in range(pos0.shape[0])]
+        if pos0 is None:
+            # the library builds the initial state at the first set_params
+            self.beads = np.ascontiguousarray(beads, dtype=np.int32)
+            chains, flat = range(len(self.beads)), None
         else:
-            chains = list(pos0)
-        self.beads = np.array([c.shape[-1] for c in chains], dtype=np.int32)
-        flat = np.ascontiguousarray(np.concatenate([np.asarray(c, np.float64).ravel()
-                                                    for c in chains]))
+            if isinstance(pos0, np.ndarray) and pos0.ndim == 3:
+                chains = [pos0[i] for i in range(pos0.shape[0])]
+            else:
+                chains = list(pos0)
+            self.beads = np.array([c.shape[-1] for c in chains], dtype=np.int32)
+            flat = np.ascontiguousarray(np.concatenate([np.asarray(c, np.float64).ravel()
+                                                        for c in chains]))
         self.offsets = np.concatenate([[0], np.cumsum(3 * self.beads.astype(np.int64))])
         prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         self.precision = prec
@@ -158,7 +165,8 @@ class Context:
         sptr = ctypes.c_void_p(stream.cuda_stream if stream is not None else 0)
         h = ctypes.c_void_p()
         rc = self.lib.dm_init_chains(ctypes.byref(h), len(chains), self.beads.ctypes.data,
-                                     flat.ctypes.data, seed, prec, sptr)
+                                     None if flat is None else flat.ctypes.data, seed, prec,
+                                     sptr)
         if rc != DM_OK:
             raise DMError(rc, self.lib.dm_last_error(None).decode())
         self.h = h

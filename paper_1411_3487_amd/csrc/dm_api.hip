@@ -13,6 +13,7 @@
 #include "../../include/dnamodes.h"
 #include "dm_fused.h"
 #include "dm_internal.h"
+#include "dm_rng.h"
 #include "dm_tables.h"
 
 namespace {
@@ -67,6 +68,7 @@ struct dm_ctx {
     size_t total = 0;                // sum of 3*beads
     std::vector<Bucket> buckets;
     bool have_params = false;
+    bool pending_init = false;       // created without positions: state built at set_params
     double T_star = 0, nu = 0, gamma_dot = 0;
     int nonlinear = 1, sample_every = 0, check_finite = 0;
     int64_t step = 0;
@@ -361,6 +363,63 @@ int check_state(dm_ctx *ctx)
     return DM_OK;
 }
 
+// Centre of mass of each of n chains of M beads (SoA positions).
+void centres(const std::vector<double> &pos, int M, int n, std::vector<double> &cm)
+{
+    for (int j = 0; j < n; ++j)
+        for (int a = 0; a < 3; ++a) {
+            double s = 0.0;
+            for (int i = 0; i < M; ++i) s += pos[(size_t)3 * M * j + (size_t)a * M + i];
+            cm[3 * j + a] = s / M;
+        }
+}
+
+// The initial state of a context created without positions (the batched
+// workloads' recipe; the paper prescribes none): chain c straight with bond
+// length bl = 1/(1 - 2 nu) along a direction uniform on the unit sphere
+// (Philox tag kTagOrient, block 0: cos(theta) = 2 U0 - 1, phi = 2 pi U1),
+// every coordinate jittered by 0.01 bl times a normal (tag kTagInit, index
+// bead n, component a), all at step 0.  Built on the host in FP64, then
+// transformed to mode amplitudes as an initial conformation given by the
+// caller would be.
+int config_state(dm_ctx *ctx, double nu)
+{
+    const double bl = 1.0 / (1.0 - 2.0 * nu), scale = 2.3283064365386962890625e-10;
+    const double two_pi = 6.283185307179586476925286766559;
+    for (Bucket &b : ctx->buckets) {
+        const int M = b.M;
+        std::vector<double> pos((size_t)3 * M * b.n), cm0((size_t)3 * b.n);
+        for (int j = 0; j < b.n; ++j) {
+            const uint32_t chain = (uint32_t)b.ids[j];
+            const dm::Block4 o = dm::noise_bits(ctx->seed, 0u, chain, 0, 0u, dm::kTagOrient);
+            const double u0 = ((double)o.v[0] + 0.5) * scale, u1 = ((double)o.v[1] + 0.5) * scale;
+            const double ct = 2.0 * u0 - 1.0, st = std::sqrt(1.0 - ct * ct), ph = two_pi * u1;
+            const double e[3] = {st * std::cos(ph), st * std::sin(ph), ct};
+            double *r = &pos[(size_t)3 * M * j];
+            for (int a = 0; a < 3; ++a)
+                for (int q = 0; 4 * q < M; ++q) {
+                    double z[4];
+                    dm::normals4_f64(dm::noise_bits(ctx->seed, (uint32_t)q, chain, 0, (uint32_t)a,
+                                                    dm::kTagInit),
+                                     z);
+                    for (int i = 4 * q; i < M && i < 4 * q + 4; ++i)
+                        r[(size_t)a * M + i] = i * bl * e[a] + 0.01 * bl * z[i - 4 * q];
+                }
+        }
+        centres(pos, M, b.n, cm0);
+        DM_HIP(ctx, hipMemcpyAsync(b.d_r, pos.data(), sizeof(double) * pos.size(),
+                                   hipMemcpyHostToDevice, ctx->stream));
+        DM_HIP(ctx, hipMemcpyAsync(b.d_cm0, cm0.data(), sizeof(double) * cm0.size(),
+                                   hipMemcpyHostToDevice, ctx->stream));
+        DM_HIP(ctx, dm::launch_gemm_f64(b.d_Afwd, b.d_r, b.d_R64, M, 3 * b.n, ctx->stream));
+        if (fused_precision(ctx->precision))
+            DM_HIP(ctx, dm::fused_pack_modes(b.fused, b.d_R64, M, b.n, ctx->stream));
+        DM_HIP(ctx, hipStreamSynchronize(ctx->stream));  // the host arrays die here
+    }
+    ctx->pending_init = false;
+    return DM_OK;
+}
+
 // One FP64 plain-form mode step of one bucket at Philox step k.
 int plain_step(dm_ctx *ctx, Bucket &b, int64_t k)
 {
@@ -388,7 +447,7 @@ int dm_init_chains(dm_ctx **out, int32_t n_chains, const int32_t *beads, const d
     if (!out) return fail(nullptr, DM_EINVAL, "out is NULL");
     *out = nullptr;
     if (n_chains <= 0) return fail(nullptr, DM_EINVAL, "n_chains must be positive");
-    if (!beads || !pos0) return fail(nullptr, DM_EINVAL, "beads and pos0 must be non-NULL");
+    if (!beads) return fail(nullptr, DM_EINVAL, "beads must be non-NULL");
     if (precision != DM_FP64 && !fused_precision(precision))
         return fail(nullptr, DM_EINVAL, "unknown precision %d", precision);
     for (int c = 0; c < n_chains; ++c) {
@@ -403,6 +462,7 @@ int dm_init_chains(dm_ctx **out, int32_t n_chains, const int32_t *beads, const d
     }
     dm_ctx *ctx = new dm_ctx();
     ctx->nchains = n_chains;
+    ctx->pending_init = pos0 == nullptr;
     ctx->precision = precision;
     ctx->seed = seed;
     ctx->stream = (hipStream_t)hip_stream;
@@ -467,15 +527,13 @@ int dm_init_chains(dm_ctx **out, int32_t n_chains, const int32_t *beads, const d
             ainv[(size_t)n * b.M] = 0.0;
             for (int p = 0; p < b.M; ++p) afwd[(size_t)p * b.M + n] = phi[(size_t)n * b.M + p];
         }
-        std::vector<double> pos(S), cm0((size_t)3 * b.n, 0.0);
-        for (int j = 0; j < b.n; ++j) {
-            const double *src = pos0 + b.user_off[j];
-            std::memcpy(&pos[(size_t)3 * b.M * j], src, sizeof(double) * 3 * b.M);
-            for (int a = 0; a < 3; ++a) {
-                double s = 0.0;
-                for (int n = 0; n < b.M; ++n) s += src[a * b.M + n];
-                cm0[3 * j + a] = s / b.M;
-            }
+        std::vector<double> pos, cm0((size_t)3 * b.n, 0.0);
+        if (pos0) {
+            pos.resize(S);
+            for (int j = 0; j < b.n; ++j)
+                std::memcpy(&pos[(size_t)3 * b.M * j], pos0 + b.user_off[j],
+                            sizeof(double) * 3 * b.M);
+            centres(pos, b.M, b.n, cm0);
         }
         hipError_t e = hipSuccess;
         auto up = [&](void *d, const void *h, size_t bytes) {
@@ -487,19 +545,20 @@ int dm_init_chains(dm_ctx **out, int32_t n_chains, const int32_t *beads, const d
         up(b.d_Ainv, ainv.data(), sizeof(double) * MM);
         up(b.d_Apos, phi.data(), sizeof(double) * MM);
         up(b.d_Afwd, afwd.data(), sizeof(double) * MM);
-        up(b.d_r, pos.data(), sizeof(double) * S);
+        if (pos0) up(b.d_r, pos.data(), sizeof(double) * S);
         up(b.d_cm0, cm0.data(), sizeof(double) * 3 * b.n);
         if (e == hipSuccess)
             e = hipMemsetAsync(b.d_acc, 0, sizeof(double) * dm::acc_width(b.M) * b.n,
                                ctx->stream);
         if (e == hipSuccess)
             e = hipMemsetAsync(b.d_tumble, 0, sizeof(double) * 2 * b.n, ctx->stream);
-        if (e == hipSuccess)
+        if (e == hipSuccess && pos0)
             e = dm::launch_gemm_f64(b.d_Afwd, b.d_r, b.d_R64, b.M, 3 * b.n, ctx->stream);
         if (e == hipSuccess && fused_precision(precision)) {
             e = dm::fused_alloc(b.fused, b.M, b.n, precision == DM_BF16X3);
             b.fused.ids = b.d_ids;
-            if (e == hipSuccess) e = dm::fused_pack_modes(b.fused, b.d_R64, b.M, b.n, ctx->stream);
+            if (e == hipSuccess && pos0)
+                e = dm::fused_pack_modes(b.fused, b.d_R64, b.M, b.n, ctx->stream);
         }
         // the host staging buffers die with this scope: finish the uploads first
         if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
@@ -554,6 +613,10 @@ int dm_set_params(dm_ctx *ctx, const dm_params *p)
     }
     const double gdot = p->gamma_dot * tunit;
     if (!std::isfinite(gdot)) return fail(ctx, DM_EINVAL, "gamma_dot is not finite");
+    if (ctx->pending_init) {
+        int rc = config_state(ctx, nu);
+        if (rc) return rc;
+    }
     for (size_t i = 0; i < ctx->buckets.size(); ++i) {
         Bucket &b = ctx->buckets[i];
         dm::ModeCoefs mc;
@@ -724,6 +787,8 @@ int dm_step_wlc(dm_ctx *ctx, int64_t n_steps, double dt_bar, double T_bar, int32
     if (!(dt_bar > 0.0) || !std::isfinite(dt_bar) || !(T_bar > 0.0) || !std::isfinite(T_bar))
         return fail(ctx, DM_EINVAL, "dt_bar and T_bar must be positive");
     if (iters < 1 || iters > 64) return fail(ctx, DM_EINVAL, "iters must be 1..64");
+    if (ctx->pending_init)
+        return fail(ctx, DM_ESTATE, "no state yet: the initial state is built by dm_set_params");
     if (!(tol >= 0.0) || !std::isfinite(tol))
         return fail(ctx, DM_EINVAL, "tol must be finite and >= 0");
     if (n_steps == 0) return DM_OK;
@@ -829,6 +894,8 @@ int dm_observables(dm_ctx *ctx, int32_t which, double *out_host, size_t out_len)
     dm_observables_size(ctx, which, &need);
     if (out_len < need || (need && !out_host))
         return fail(ctx, DM_EINVAL, "output needs %zu doubles, got %zu", need, out_len);
+    if (ctx->pending_init)
+        return fail(ctx, DM_ESTATE, "no state yet: the initial state is built by dm_set_params");
     double *o = out_host;
     if (which & (DM_OBS_CHAIN | DM_OBS_MODES)) {
         int rc = observe(ctx, 0, ctx->stream);
@@ -891,6 +958,8 @@ int dm_observables(dm_ctx *ctx, int32_t which, double *out_host, size_t out_len)
 int dm_get_positions(dm_ctx *ctx, double *dst, int32_t dst_on_device)
 {
     if (!ctx || !dst) return ctx ? fail(ctx, DM_EINVAL, "dst is NULL") : DM_EINVAL;
+    if (ctx->pending_init)
+        return fail(ctx, DM_ESTATE, "no state yet: the initial state is built by dm_set_params");
     for (Bucket &b : ctx->buckets) {
         int rc = bucket_positions(ctx, b, ctx->stream);
         if (rc) return rc;
@@ -914,6 +983,8 @@ int dm_get_positions(dm_ctx *ctx, double *dst, int32_t dst_on_device)
 int dm_get_modes(dm_ctx *ctx, double *dst)
 {
     if (!ctx || !dst) return ctx ? fail(ctx, DM_EINVAL, "dst is NULL") : DM_EINVAL;
+    if (ctx->pending_init)
+        return fail(ctx, DM_ESTATE, "no state yet: the initial state is built by dm_set_params");
     for (Bucket &b : ctx->buckets) {
         if (fused_precision(ctx->precision))
             DM_HIP(ctx, dm::fused_unpack_modes(b.fused, b.d_R64, b.M, b.n, ctx->stream));
@@ -956,6 +1027,8 @@ int dm_save_state(dm_ctx *ctx, void *buf, size_t *len)
         return DM_OK;
     }
     if (*len < need) return fail(ctx, DM_EINVAL, "state buffer needs %zu bytes", need);
+    if (ctx->pending_init)
+        return fail(ctx, DM_ESTATE, "no state yet: the initial state is built by dm_set_params");
     char *p = (char *)buf;
     StateHeader h{kStateMagic, ctx->step, ctx->nchains, ctx->precision,
                   (int32_t)ctx->buckets.size(), 0};
@@ -1021,6 +1094,7 @@ int dm_load_state(dm_ctx *ctx, const void *buf, size_t len)
             DM_HIP(ctx, hipMemsetAsync(b.d_ccount, 0, sizeof(double) * b.n, ctx->stream));
     DM_HIP(ctx, hipStreamSynchronize(ctx->stream));
     ctx->step = h.step;
+    ctx->pending_init = false;
     return DM_OK;
 }
 

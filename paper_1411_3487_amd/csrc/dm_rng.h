@@ -15,7 +15,14 @@
 
 namespace dm {
 
-enum : uint32_t { kTagMode = 0u, kTagEuler = 1u, kTagMC = 2u, kTagWLC = 3u };
+enum : uint32_t {
+    kTagMode = 0u,
+    kTagEuler = 1u,
+    kTagMC = 2u,
+    kTagWLC = 3u,
+    kTagInit = 4u,    // jitter of the initial state (index = bead)
+    kTagOrient = 5u,  // direction of an initial chain (index 0)
+};
 
 struct Block4 {
     uint32_t v[4];

@@ -62,7 +62,8 @@ def test_null_pointers_are_rejected():
     lib = _lib.load()
     h = ctypes.c_void_p()
     b = np.array([64], dtype=np.int32)
-    assert lib.dm_init_chains(ctypes.byref(h), 1, b.ctypes.data, None, 0, 0, None) == _lib.DM_EINVAL
+    # beads is required; pos0 may be NULL (the library's own initial state)
+    assert lib.dm_init_chains(ctypes.byref(h), 1, None, None, 0, 0, None) == _lib.DM_EINVAL
     assert lib.dm_init_chains(None, 1, b.ctypes.data, None, 0, 0, None) == _lib.DM_EINVAL
     assert lib.dm_step_modes(None, 1) == _lib.DM_EINVAL
     assert lib.dm_destroy(None) == _lib.DM_EINVAL

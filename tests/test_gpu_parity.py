@@ -275,3 +275,37 @@ def test_positions_to_device_buffer():
         torch.cuda.synchronize()
         flat = np.concatenate([h.ravel() for h in host])
         assert np.array_equal(dev.cpu().numpy(), flat)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+def test_library_initial_state_matches_oracle(prec):
+    """A context created without positions builds the batched workloads'
+    initial state itself (straight chains, Philox-uniform directions, 0.01 b
+    jitter; Philox tags 5 and 4) at its first dm_set_params: the positions
+    equal the oracle's generator of the same recipe, and 100 mode steps from
+    them follow the oracle.  Before dm_set_params the state cannot be read."""
+    B, M, dtau, n = 12, 128, 50.0, 100
+    with Context(None, seed=1, precision=prec, beads=[M] * B) as ctx:
+        with pytest.raises(DMError):
+            ctx.positions()
+        ctx.set_params([M], [dtau], T_star=TS, nu=NU)
+        x0 = ctx.positions()
+        ctx.step_modes(n)
+        x = ctx.positions()
+    want0 = oracle.config_chains(M, B, NU, seed=1)
+    err0 = rel_pos_err(x0, want0)
+    ref = oracle_positions(want0, dtau, n, seed=1)
+    err = rel_pos_err(x, ref)
+    print(f"{prec}: initial state err {err0:.2e}, after {n} steps {err:.2e}")
+    assert err0 < (1e-13 if prec == "fp64" else 1e-6)
+    assert err < (FP64_TOL if prec == "fp64" else 1e-3)
+
+
+def test_library_initial_state_of_an_uneven_ensemble():
+    beads = [64, 128, 64, 256, 128]
+    with Context(None, seed=3, precision="fp64", beads=beads) as ctx:
+        ctx.set_params([64, 128, 256], [10.0, 50.0, 100.0], T_star=TS, nu=NU)
+        got = ctx.positions()
+    for c, M in enumerate(beads):
+        want = oracle.config_chains(M, 1, NU, seed=3, chain_ids=[c])
+        assert rel_pos_err(got[c][None], want) < 1e-13, c

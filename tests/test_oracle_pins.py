@@ -735,3 +735,39 @@ def test_wlc_trimer_angle_follows_the_constrained_ensemble():
     se = v.std() / np.sqrt(v.size)
     assert abs(v.mean() - rigid) < 4 * se, (v.mean(), rigid, se)
     assert abs(stiff - rigid) > 4 * se
+
+
+# ---------------------------------------------------------------- initial state
+def test_config_chains_are_straight_with_uniform_orientation_and_jitter():
+    """The batched workloads' initial state: per chain a straight line of
+    bond length b along a direction uniform on the sphere, each coordinate
+    jittered by 0.01 b times an independent standard normal.  Direction from
+    the mean bond (cos(theta) and phi uniform: Kolmogorov-Smirnov); jitter
+    from the second differences x_{n+1} - 2 x_n + x_{n-1}, which remove the
+    line exactly and are 0.01 b (z_{n+1} - 2 z_n + z_{n-1}): variance 6, lag-1
+    correlation -2/3, lag-2 correlation 1/6 for white z.  Keyed by the chain
+    index, not by the position in the batch."""
+    B, M, nu = 3000, 32, NU
+    b = 1.0 / (1.0 - 2.0 * nu)
+    x = oracle.config_chains(M, B, nu, seed=1)
+    e = (x[:, :, -1] - x[:, :, 0]) / ((M - 1) * b)
+    assert np.abs(np.linalg.norm(e, axis=1) - 1).max() < 0.005
+    e /= np.linalg.norm(e, axis=1, keepdims=True)
+    assert scipy.stats.kstest(e[:, 2], "uniform", args=(-1, 2)).pvalue > 1e-3
+    phi = np.mod(np.arctan2(e[:, 1], e[:, 0]), 2 * np.pi)
+    assert scipy.stats.kstest(phi, "uniform", args=(0, 2 * np.pi)).pvalue > 1e-3
+    d2 = (x[:, :, 2:] - 2 * x[:, :, 1:-1] + x[:, :, :-2]) / (0.01 * b)
+    n = d2.size
+    assert abs(d2.mean()) < 5 * np.sqrt(6.0 / n)
+    assert d2.var() == pytest.approx(6.0, rel=0.01)
+    r1 = (d2[:, :, 1:] * d2[:, :, :-1]).mean() / d2.var()
+    r2 = (d2[:, :, 2:] * d2[:, :, :-2]).mean() / d2.var()
+    assert r1 == pytest.approx(-2.0 / 3.0, abs=0.01)
+    assert r2 == pytest.approx(1.0 / 6.0, abs=0.01)
+    assert scipy.stats.kstest(d2[:, :, ::3].ravel() / np.sqrt(6.0), "norm").pvalue > 1e-4
+    # components independent: no correlation of the jitter across x, y, z
+    c = np.corrcoef(d2[:, 0].ravel(), d2[:, 1].ravel())[0, 1]
+    assert abs(c) < 0.01
+    sub = oracle.config_chains(M, 2, nu, seed=1, chain_ids=[17, 2999])
+    assert np.array_equal(sub, x[[17, 2999]])
+    assert not np.allclose(oracle.config_chains(M, 2, nu, seed=2), x[:2])
