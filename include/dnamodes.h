@@ -335,6 +335,32 @@ int dm_coarse_grain(double r, double y, int32_t k, double *T_star_k, double *nu_
    Errors: as dm_coarse_grain. */
 int dm_coarse_grain_time(double r, double y, int32_t k, double *c_k);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, tight serving loops, harnesses that forbid hipMalloc): the FP64
+   plain-form mode step of dm_step_modes for one chain length, without a
+   context.  R_dev (device, caller-owned, 16-byte aligned) holds n_chains
+   chains of M mode amplitudes R_p in the SoA layout (3*M doubles per
+   chain, p = 0..M-1) and is advanced in place by n_steps steps at Philox
+   steps step0 .. step0 + n_steps - 1; chain j draws its noise as chain index
+   chain0 + j, so a call reproduces dm_step_modes on those chains of a
+   context.  Reduced units: T_star, nu, dtau (= Delta tau), gamma_dot; tables
+   and coefficients are built on the device at every call.  No allocation:
+   the tables, the chain indices and the two work buffers live in one fixed
+   device array of DM_STATIC_SCRATCH_BYTES per GPU, held from the first use
+   until the process ends; it needs 8 (2 M^2 + 3 M + 6 M n_chains) +
+   4 n_chains bytes (each part rounded up to 256), e.g. 4096 chains of 256
+   beads.  Calls that overlap on one GPU share that array and race; calls on
+   one stream are ordered.  Asynchronous on hip_stream.  Errors (message in
+   dm_last_error(NULL)): DM_EINVAL for a size beyond the array, M outside
+   2..2048, n_chains < 1, nu outside [0, 1/2), T* or dtau not positive,
+   n_steps or step0 < 0, a misaligned or NULL R_dev; DM_EHIP. */
+#define DM_STATIC_SCRATCH_BYTES (64u << 20)
+int dm_step_modes_f64_static(double *R_dev, int32_t n_chains, int32_t M,
+                             double T_star, double nu, double dtau,
+                             double gamma_dot, int32_t nonlinear, uint64_t seed,
+                             uint32_t chain0, int64_t step0, int64_t n_steps,
+                             void *hip_stream);
+
 /* Synchronise the context's stream. */
 int dm_sync(dm_ctx *ctx);
 

@@ -67,7 +67,7 @@ EXPORTS = ["dm_init_chains", "dm_set_params", "dm_step_modes", "dm_step_euler", 
            "dm_observables", "dm_observables_size", "dm_get_positions", "dm_get_modes",
            "dm_save_state", "dm_load_state", "dm_get_step", "dm_get_tiling",
            "dm_tuning_report", "dm_coarse_grain", "dm_coarse_grain_time", "dm_sync", "dm_destroy",
-           "dm_last_error"]
+           "dm_last_error", "dm_step_modes_f64_static"]
 
 _lib = None
 
@@ -107,6 +107,9 @@ def load(path: str = LIB_PATH):
         "dm_sync": ([vp], ctypes.c_int),
         "dm_destroy": ([vp], ctypes.c_int),
         "dm_last_error": ([vp], ctypes.c_char_p),
+        "dm_step_modes_f64_static": ([vp, i32, i32, ctypes.c_double, ctypes.c_double,
+                                      ctypes.c_double, ctypes.c_double, i32, u64,
+                                      ctypes.c_uint32, i64, i64, vp], ctypes.c_int),
     }
     for name, (args, res) in sigs.items():
         fn = getattr(lib, name)

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdnamodes.so")
-SOURCES = ["dm_api.hip", "dm_plain.hip", "dm_fused.hip", "dm_tables.cpp"]
+SOURCES = ["dm_api.hip", "dm_plain.hip", "dm_fused.hip", "dm_static.hip", "dm_tables.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # Packed FP32 VALU forms are disabled for all device code (-packed-fp32-ops).

@@ -57,6 +57,10 @@ struct Bucket {
 
 }  // namespace
 
+namespace dm {
+void set_ctxless_error(const char *msg) { g_init_error = msg; }
+}  // namespace dm
+
 struct dm_ctx {
     int nchains = 0;
     int precision = DM_FP64;

@@ -38,6 +38,10 @@ __device__ inline void corr_update(double *ring, double *count, double *corr, co
     *count = (double)(i + 1);
 }
 
+// Message that dm_last_error(NULL) returns (errors of calls without a
+// context), dm_api.hip.
+void set_ctxless_error(const char *msg);
+
 // Plain-form (FP64) kernels, dm_plain.hip.  Every launcher only enqueues on
 // `st` and returns the launch status.
 

@@ -16,7 +16,7 @@ HEADER = os.path.join(ROOT, "include", "dnamodes.h")
 def declared_functions():
     src = open(HEADER).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(dm_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(dm_[a-z0-9_]+)\s*\(", src)))
 
 
 def test_library_exports_every_declared_symbol():
@@ -118,3 +118,22 @@ def test_coarse_grain_reproduces_factin_table4():
         assert 1.010 < nu / nu_t < 1.016, k
         t2, nu2 = _lib.coarse_grain(1579.2, 7.65e7, int(k))
         assert nu2 == pytest.approx(nu_t, rel=1e-3), k
+
+
+@pytest.mark.parametrize("ptr,B,M,nu,dtau", [(256, 100000, 256, 0.35, 100.0),   # beyond the array
+                                             (8, 4, 64, 0.35, 10.0),            # misaligned
+                                             (0, 4, 64, 0.35, 10.0),            # NULL
+                                             (256, 4, 1, 0.35, 10.0),           # M < 2
+                                             (256, 4, 64, 0.5, 10.0),           # nu = 1/2
+                                             (256, 4, 64, 0.35, 0.0)])          # dtau = 0
+def test_static_step_rejects_bad_arguments_without_gpu(ptr, B, M, nu, dtau):
+    """dm_step_modes_f64_static checks its arguments (and the size of its
+    fixed work array) before any HIP call."""
+    lib = _lib.load()
+    rc = lib.dm_step_modes_f64_static(ctypes.c_void_p(ptr), B, M, 0.034, nu, dtau, 0.0, 1, 0,
+                                      0, 0, 1, None)
+    assert rc == _lib.DM_EINVAL
+    msg = lib.dm_last_error(None)
+    assert len(msg) > 0
+    if B == 100000:
+        assert b"DM_STATIC_SCRATCH_BYTES" in msg
