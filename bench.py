@@ -28,13 +28,15 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--workload", default="modes",
                     choices=["modes", "uneven", "shear", "mc", "dtmax", "dtmax_t", "wlc", "euler",
-                             "stats", "fp64"],
+                             "stats", "fp64", "coarse"],
                     help="modes: 4096 x 256 bp (the headline line); uneven: 8192 chains of "
                          "64..512 bp in one launch; shear: 2048 x 256 bp under simple shear "
                          "at Wi = 1, 10, 100 (tumbling and extension, FP32 vs FP64); mc: "
                          "Metropolis sweeps of 4096 x 256 bp; dtmax: equilibrium values of the "
                          "mode dynamics against Monte Carlo over a range of time steps")
     ap.add_argument("--shear-steps", type=int, default=1000000)
+    ap.add_argument("--coarse-chains", type=int, default=2048)
+    ap.add_argument("--coarse-samples", type=int, default=32768)
     ap.add_argument("--stats-steps", type=int, default=100000,
                     help="steps of each run of the stats workload")
     ap.add_argument("--profile-launches", type=int, default=0, metavar="N",
@@ -351,6 +353,76 @@ def fp64_workload(args):
                                              f"{args.steps} steps, no observables"}}))
 
 
+def coarse_workload(args):
+    """Sec. VI, Fig. 5: the end-to-end vector's mean square displacement
+    against real time for a chain of 256 basepairs (256 beads, k = 1) and for
+    the same chain as 128 dimerised basepairs (128 beads, k = 2), both with
+    the parameters of Eq. (x4) for r = l_p/a = 120, y = l_p K_0/kT = 12000
+    (k = 1: T* = 0.034, nu = 6/17; k = 2: T*_2 = 0.008, nu_2 = 0.1875), so
+    that both follow the same force-extension curve.  Real time t = c_k tau_k
+    with c_k = k^3 T*_k (1 - 2 nu_k)^2 a^2 xi / kT (Eq. g2 with a_k = k a and
+    xi_k = k xi); lengths in basepairs a via d_k = k a (1 - 2 nu_k).  Each
+    chain relaxes from the library's straight initial state for 4 / zeta_1
+    (same real time for both), then samples every 100 steps on a common
+    real-time grid; the msd of L at lag l is 2 (<L.L> at lag 0 - <L.L> at lag
+    l) from the lag correlators.  k = 2 runs at two time steps (the one that
+    matches the k = 1 grid with 100 steps per sample, and a quarter of it
+    with 400) to show its curve is converged in the time step."""
+    import numpy as np
+    import torch
+    from paper_1411_3487_amd import Context, coarse_grain
+    from paper_1411_3487_amd._lib import coarse_grain_time
+    torch.cuda.set_device(0)
+    r, y, B, K = 120.0, 12000.0, args.coarse_chains, 14
+    nsamp = args.coarse_samples
+    runs = [(1, 256, 100.0, 100), (2, 128, None, 100), (2, 128, None, 400)]
+    c1 = coarse_grain_time(r, y, 1)
+    grid = 100 * 100.0 * c1                      # real time between samples, a^2 xi / kT
+    out = []
+    for k, M, dtau, se in runs:
+        T, nu = coarse_grain(r, y, k)
+        ck = coarse_grain_time(r, y, k)
+        if dtau is None:
+            dtau = grid / (se * ck)
+        z1 = 16 * nu * np.sin(np.pi / (2 * M)) ** 4
+        relax = int(round(4.0 / z1 / dtau / se)) * se
+        t0 = time.perf_counter()
+        with Context(None, seed=5, precision=args.precision, beads=[M] * B) as ctx:
+            ctx.set_params([M], [dtau], T_star=T, nu=nu, sample_every=se, corr_lags=K,
+                           use_graphs=True, autotune=True)
+            steps_with_progress(ctx, relax, f"k={k} dtau={dtau:.4g} relax", chunk=200 * se * 100)
+            ctx.accumulators(reset=True)
+            steps_with_progress(ctx, nsamp * se, f"k={k} dtau={dtau:.4g} sample",
+                                chunk=200 * se * 100)
+            a = ctx.accumulators()[0]
+        d2 = (k * (1.0 - 2.0 * nu)) ** 2          # (d_k / a)^2
+        c = a["corr"][:K]
+        LL = c[:, 0] / np.maximum(c[:, 3], 1)
+        msd = 2.0 * (LL[0] - LL) * d2
+        lags = np.array([0] + [2 ** (j - 1) for j in range(1, K)])
+        out.append({"k": k, "beads": M, "T_star": T, "nu": nu, "dtau": dtau,
+                    "steps_per_sample": se, "c_k_ps": ck * 52.0,
+                    "relax_steps": relax, "sample_steps": nsamp * se,
+                    "L2_a2": a["L2"] / a["n_samples"] / B * d2,
+                    "lag_samples": lags.tolist(), "msd_L_a2": msd.tolist(),
+                    "seconds": round(time.perf_counter() - t0, 1)})
+        print(f"# k={k} M={M} dtau={dtau:.4g}: <L^2> = {out[-1]['L2_a2']:.1f} a^2, "
+              f"{out[-1]['seconds']} s", file=sys.stderr, flush=True)
+    ref = np.array(out[0]["msd_L_a2"])
+    t_us = np.array(out[0]["lag_samples"]) * grid * 52.0e-6
+    rows = []
+    for o in out[1:]:
+        m = np.array(o["msd_L_a2"])
+        ratio = [float(m[j] / ref[j]) if ref[j] > 0 else None for j in range(K)]
+        ok = all(abs(x - 1) <= 0.05 for x in ratio[1:] if x is not None)
+        rows.append({"k": o["k"], "dtau": o["dtau"], "ratio_to_k1": ratio, "within_5pct": ok,
+                     "L2_ratio_to_k1": o["L2_a2"] / out[0]["L2_a2"]})
+    print(json.dumps({"workload": f"Fig. 5: end-to-end msd, {B} chains of 256 bp (k = 1) vs "
+                                  f"128 dimers (k = 2), {nsamp} samples, {args.precision}",
+                      "real_time_per_sample_ns": grid * 52.0e-3, "lag_time_us": t_us.tolist(),
+                      "runs": out, "comparison": rows}))
+
+
 def profile_launches(args):
     """N launches of 200 mode steps of the default workload, no sampling."""
     import torch
@@ -629,18 +701,24 @@ WLC_FLOPS_PER_BOND_ITER = 85
 
 
 def wlc_workload(args):
-    """Sec. 6a: the largest time step of the inextensible limit (Eqs. y2-y14)
-    for N = 63 at the persistence length of dsDNA (T-bar = a / l_p = 1/114.4).
-    From exact discrete-wormlike-chain starts: the time averages of <L^2> and
-    of the mean square distance of the middle bead from the centre of mass
-    must stay within 5 % of their closed forms, and the mean square
-    displacement of the middle bead (about the centre of mass) at times
-    0.002 * 2^k up to 1.024 within 5 % of the smallest time step's.  The extensible model
-    under the bead Euler scheme is safe at dtau = 0.1 (Sec. 3a), i.e. at
-    dtau-bar = nu dtau = 0.035."""
+    """Sec. VII.A: the largest time step of the inextensible limit (Eqs.
+    y2-y14) for N = 63 at the persistence length of dsDNA (T-bar = a / l_p =
+    1/114.4), for two forms of the tension cycle (forces at the midpoint
+    bonds iterated to convergence; forces at the bonds of the start of the
+    step with three fixed passes).  From exact discrete-wormlike-chain
+    starts, each time step runs to tau-bar = 1.024 and is accepted while
+    every check stays within 5 %: the time averages of <L^2> and of the
+    middle bead's squared distance from the centre of mass against their
+    closed forms (set by slow modes, which these runs do not relax: they
+    only show that the step keeps the ensemble), the local bending
+    <1 - cos> (it relaxes within the run) and the middle bead's msd about
+    the centre of mass at tau-bar = 0.002 * 2^k against the smallest step's,
+    and the bonds within 1 % of unit length.  The extensible model under the
+    bead Euler scheme is safe at dtau = 0.1 (Sec. III.A), i.e. at dtau-bar =
+    nu dtau = 0.035."""
     import numpy as np
     import torch
-    from paper_1411_3487_amd import Context, NU_DSDNA
+    from paper_1411_3487_amd import Context, NU_DSDNA, dtmax
     from paper_1411_3487_amd.inputs import unit_chains
     torch.cuda.set_device(0)
     B, M, T = 8192, 64, 1.0 / 114.4
@@ -656,46 +734,56 @@ def wlc_workload(args):
     def rel_mid(x):
         return x[:, :, mid] - x.mean(axis=2)
     dm0 = rel_mid(pos0)
-    rows, ref = [], None
-    for dt in [2e-5, 5e-5, 1e-4, 2e-4, 5e-4, 1e-3, 2e-3, 4e-3, 8e-3, 1.6e-2, 3.2e-2, 6.4e-2]:
-        t0 = time.perf_counter()
-        l2, dm, bend, msd, fin, done = [], [], [], {}, True, 0
-        with Context(pos0, seed=13, precision="fp64") as ctx:
-            for t in times:
-                n = int(round(t / dt)) - done
-                if n <= 0:
-                    continue
-                ctx.step_wlc(n, dt, T, iters=16, tol=1e-12)
-                done += n
-                x = ctx.positions()
-                fin = fin and bool(np.all(np.isfinite(x)))
-                L = x[:, :, -1] - x[:, :, 0]
-                d = rel_mid(x)
-                u = np.diff(x, axis=2)
-                bend.append(1 - (u[:, :, 1:] * u[:, :, :-1]).sum(axis=1).mean())
-                l2.append((L * L).sum(axis=1).mean())
-                dm.append((d * d).sum(axis=1).mean())
-                msd[t] = float(((d - dm0) ** 2).sum(axis=1).mean())
-            bond_err = float(np.abs(np.linalg.norm(np.diff(x, axis=2), axis=1) - 1).max())
-        if ref is None:
-            ref = msd
-        r = {"dtau_bar": dt, "steps": done, "L2_ratio": float(np.mean(l2) / L2),
-             "dmid2_ratio": float(np.mean(dm) / d2),
-             "bend_ratio": float(np.mean(bend) / (1 - c)),
-             "msd_mid_ratio": {f"{t:g}": msd[t] / ref[t] for t in msd},
-             "bond_err": bond_err, "finite": fin,
-             "seconds": round(time.perf_counter() - t0, 2)}
-        r["within_5pct"] = bool(fin and abs(r["L2_ratio"] - 1) < 0.05
-                                and abs(r["dmid2_ratio"] - 1) < 0.05
-                                and all(abs(v - 1) < 0.05 for v in r["msd_mid_ratio"].values()))
-        rows.append(r)
-        print(f"# dt_bar={dt}: {r}", file=sys.stderr, flush=True)
-    ok = []
-    for r in rows:
-        if not r["within_5pct"]:
-            break
-        ok.append(r["dtau_bar"])
-    wlc_max = ok[-1] if ok else None
+    grid = [2e-5, 5e-5, 1e-4, 2e-4, 5e-4, 1e-3, 2e-3, 4e-3, 8e-3, 1.6e-2, 3.2e-2, 6.4e-2,
+            0.128, 0.256]
+    # the two forms of the tension cycle: forces and tensions along the
+    # midpoint bonds (Eq. y14), iterated to convergence; and along the bonds
+    # of the start of the step with three fixed passes (the cycle as first
+    # written, "typically two or three steps")
+    variants = {"midpoint_converged": dict(midpoint=True, iters=16, tol=1e-12),
+                "start_bonds_3_passes": dict(midpoint=False, iters=3, tol=0.0)}
+    scans = {}
+    for vname, kw in variants.items():
+        rows, ref, bend_ref = [], None, None
+        for dt in grid:
+            t0 = time.perf_counter()
+            l2, dm, bend, msd, fin, done = [], [], [], {}, True, 0
+            with Context(pos0, seed=13, precision="fp64") as ctx:
+                for t in times:
+                    n = int(round(t / dt)) - done
+                    if n <= 0:
+                        continue
+                    ctx.step_wlc(n, dt, T, **kw)
+                    done += n
+                    x = ctx.positions()
+                    fin = fin and bool(np.all(np.isfinite(x)))
+                    L = x[:, :, -1] - x[:, :, 0]
+                    d = rel_mid(x)
+                    u = np.diff(x, axis=2)
+                    bend.append(1 - (u[:, :, 1:] * u[:, :, :-1]).sum(axis=1).mean())
+                    l2.append((L * L).sum(axis=1).mean())
+                    dm.append((d * d).sum(axis=1).mean())
+                    msd[t] = float(((d - dm0) ** 2).sum(axis=1).mean())
+                bond_err = float(np.abs(np.linalg.norm(np.diff(x, axis=2), axis=1) - 1).max())
+            if ref is None:
+                ref, bend_ref = msd, float(np.mean(bend))
+            r = {"dtau_bar": dt, "steps": done, "L2_ratio": float(np.mean(l2) / L2),
+                 "dmid2_ratio": float(np.mean(dm) / d2),
+                 "bend_ratio_to_theory": float(np.mean(bend) / (1 - c)),
+                 "bend_ratio_to_smallest_step": float(np.mean(bend) / bend_ref),
+                 "msd_mid_ratio": {f"{t:g}": msd[t] / ref[t] for t in msd},
+                 "bond_err": bond_err, "finite": fin,
+                 "seconds": round(time.perf_counter() - t0, 2)}
+            checks = [r["L2_ratio"], r["dmid2_ratio"], r["bend_ratio_to_smallest_step"],
+                      *r["msd_mid_ratio"].values()]
+            r["within_5pct"] = bool(fin and bond_err < 0.01
+                                    and all(abs(v - 1) < 0.05 for v in checks))
+            rows.append(r)
+            print(f"# {vname} dt_bar={dt}: {r}", file=sys.stderr, flush=True)
+        scans[vname] = {"rows": rows, "dtau_bar_max": dtmax.contiguous_dtau_max(
+            [r["dtau_bar"] for r in rows], [r["within_5pct"] for r in rows])}
+    rows = scans["midpoint_converged"]["rows"]
+    wlc_max = scans["midpoint_converged"]["dtau_bar_max"]
     ext = 0.1 * NU_DSDNA
     # throughput of the stepper: HIP events around one call on the context's stream
     stream = torch.cuda.current_stream()
@@ -735,7 +823,8 @@ def wlc_workload(args):
     print(json.dumps({"workload": f"inextensible limit, {B} chains of {M} beads, T_bar = 1/114.4",
                       "theory": {"L2": L2, "dmid2": d2, "bond_cos": c},
                       "msd_mid_ref": {f"{t:g}": v for t, v in ref.items()},
-                      "runs": rows, "stepper": perf, "dtau_bar_max_wlc": wlc_max,
+                      "scans": scans, "stepper": perf, "dtau_bar_max_wlc": wlc_max,
+                      "dtau_bar_max_start_bonds": scans["start_bonds_3_passes"]["dtau_bar_max"],
                       "dtau_bar_max_extensible_euler": ext,
                       "gain": (ext / wlc_max) if wlc_max else None}))
 
@@ -756,6 +845,8 @@ def main():
         return stats_workload(args)
     if args.workload == "fp64" and args.gpus == 1:
         return fp64_workload(args)
+    if args.workload == "coarse" and args.gpus == 1:
+        return coarse_workload(args)
     if args.profile_launches:
         return profile_launches(args)
     if args.workload != "modes" and args.gpus == 1:

@@ -253,14 +253,17 @@ int dm_step_euler(dm_ctx *ctx, int64_t n_steps, double dtau);
    wavefront per chain with the chain in registers up to M = 64 and in LDS
    up to M = 341 (tensions by cyclic reduction), one thread per chain beyond
    (Thomas sweep, global scratch allocated on first use); noise tag 3
-   (index = bead).
+   (index = bead).  midpoint != 0: forces and tensions at the midpoint
+   bonds u^m_n as above (Eq. y14, the time-symmetric form); midpoint == 0:
+   at the bonds u_n of the start of the step, the constraint rows still
+   (u_n + u'_n) . du_n = 0 (the cycle of Eqs. y9-y13 as first written).
    The state is converted from and back to mode amplitudes once per call.
    Without metric pseudo-forces the scheme samples the constrained ensemble
    exp(-H/T_bar) sqrt(det G), G the constraint metric.  Errors: DM_EINVAL
    (n_steps < 0, dt_bar or T_bar <= 0, iters outside 1..64, tol < 0 or not
    finite), DM_ENONFINITE. */
 int dm_step_wlc(dm_ctx *ctx, int64_t n_steps, double dt_bar, double T_bar,
-                int32_t iters, double tol);
+                int32_t iters, double tol, int32_t midpoint);
 
 /* Metropolis Monte Carlo in the mode representation, the paper's benchmark
    for equilibrium values (Sec. 6: large steps in the slow modes, small in

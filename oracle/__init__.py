@@ -69,7 +69,7 @@ def _load():
         "orc_energy": (_d, [_i, _d, _p]),
         "orc_set_threads": (None, [_i]),
         "orc_mc_sweeps": (None, [_i, _i, _p, _p, _d, _d, _d, _u64, _i64, _i64, _p]),
-        "orc_step_wlc": (None, [_i, _i, _p, _p, _d, _d, _i, _d, _u64, _i64, _i64]),
+        "orc_step_wlc": (None, [_i, _i, _p, _p, _d, _d, _i, _d, _i, _u64, _i64, _i64]),
         "orc_chain_observables": (None, [_i, _p, _p]),
         "orc_config_chains": (None, [_i, _i, _p, _d, _u64, _p]),
     }
@@ -206,7 +206,7 @@ def step_euler(pos, nu, T_star, dtau, n_steps, seed=0, step0=0, chain_ids=None,
 
 
 def step_wlc(pos, T_bar, dt, n_steps, iters=3, seed=0, step0=0, chain_ids=None,
-             tol=0.0) -> np.ndarray:
+             tol=0.0, midpoint=True) -> np.ndarray:
     """Advance positions (B, 3, M) of unit-bond chains by n_steps steps of the
     nu -> 0 (inextensible) limit, Eqs. (y2)-(y14); returns a copy.  The
     tension cycle runs at most `iters` times, and with tol > 0 stops once a
@@ -216,7 +216,8 @@ def step_wlc(pos, T_bar, dt, n_steps, iters=3, seed=0, step0=0, chain_ids=None,
     B, _, M = pos.shape
     ids = np.arange(B, dtype=np.uint32) if chain_ids is None else \
         np.ascontiguousarray(chain_ids, dtype=np.uint32)
-    lib.orc_step_wlc(M, B, _ptr(ids), _ptr(pos), T_bar, dt, iters, tol, seed, step0, n_steps)
+    lib.orc_step_wlc(M, B, _ptr(ids), _ptr(pos), T_bar, dt, iters, tol,
+                     1 if midpoint else 0, seed, step0, n_steps)
     return pos
 
 

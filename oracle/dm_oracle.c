@@ -458,8 +458,8 @@ static void wlc_solve(int N, const double *a, const double *b, const double *c,
 }
 
 void orc_step_wlc(int M, int n_chains, const uint32_t *chain_id, double *pos,
-                  double T_bar, double dt, int iters, double tol, uint64_t seed,
-                  int64_t step0, int64_t n_steps)
+                  double T_bar, double dt, int iters, double tol, int midpoint,
+                  uint64_t seed, int64_t step0, int64_t n_steps)
 {
     const int N = M - 1;
     const double amp = sqrt(2.0 * T_bar * dt);
@@ -499,7 +499,10 @@ void orc_step_wlc(int M, int n_chains, const uint32_t *chain_id, double *pos,
                             w[3 * n + a] = u[3 * n + a] + un[3 * n + a];
                             s2 += w[3 * n + a] * w[3 * n + a];
                         }
-                        for (int a = 0; a < 3; ++a) um[3 * n + a] = w[3 * n + a] / sqrt(s2);
+                        /* Eq. (y14); or, with midpoint == 0, the bond at the
+                           start of the step (forces as first written in y8, y9) */
+                        for (int a = 0; a < 3; ++a)
+                            um[3 * n + a] = midpoint ? w[3 * n + a] / sqrt(s2) : u[3 * n + a];
                     }
                     /* bending gradient on each bond, at the midpoint */
                     for (int n = 1; n <= N; ++n)

@@ -34,8 +34,8 @@ void orc_step_euler(int M, int n_chains, const uint32_t *chain_id, double *pos,
 double orc_energy(int M, double nu, const double *pos);
 void orc_set_threads(int n);
 void orc_step_wlc(int M, int n_chains, const uint32_t *chain_id, double *pos,
-                  double T_bar, double dt, int iters, double tol, uint64_t seed,
-                  int64_t step0, int64_t n_steps);
+                  double T_bar, double dt, int iters, double tol, int midpoint,
+                  uint64_t seed, int64_t step0, int64_t n_steps);
 void orc_mc_sweeps(int M, int n_chains, const uint32_t *chain_id, double *R,
                    double nu, double T_star, double scale, uint64_t seed,
                    int64_t step0, int64_t n_sweeps, int64_t *accepted);

@@ -89,7 +89,7 @@ def load(path: str = LIB_PATH):
         "dm_step_modes": ([vp, i64], ctypes.c_int),
         "dm_step_euler": ([vp, i64, ctypes.c_double], ctypes.c_int),
         "dm_step_mc": ([vp, i64, ctypes.c_double, ctypes.POINTER(i64)], ctypes.c_int),
-        "dm_step_wlc": ([vp, i64, ctypes.c_double, ctypes.c_double, i32, ctypes.c_double],
+        "dm_step_wlc": ([vp, i64, ctypes.c_double, ctypes.c_double, i32, ctypes.c_double, i32],
                         ctypes.c_int),
         "dm_observables": ([vp, i32, vp, sz], ctypes.c_int),
         "dm_observables_size": ([vp, i32, ctypes.POINTER(sz)], ctypes.c_int),
@@ -243,8 +243,9 @@ class Context:
         self._check(self.lib.dm_step_euler(self.h, n_steps, dtau))
 
     def step_wlc(self, n_steps: int, dt_bar: float, T_bar: float, iters: int = 8,
-                 tol: float = 0.0):
-        self._check(self.lib.dm_step_wlc(self.h, n_steps, dt_bar, T_bar, iters, tol))
+                 tol: float = 0.0, midpoint: bool = True):
+        self._check(self.lib.dm_step_wlc(self.h, n_steps, dt_bar, T_bar, iters, tol,
+                                         1 if midpoint else 0))
 
     def step_mc(self, n_sweeps: int, step_scale: float = 3.0) -> int:
         """Metropolis sweeps; returns the number of accepted proposals."""

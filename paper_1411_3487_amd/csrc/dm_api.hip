@@ -784,7 +784,7 @@ int dm_step_euler(dm_ctx *ctx, int64_t n_steps, double dtau)
 }
 
 int dm_step_wlc(dm_ctx *ctx, int64_t n_steps, double dt_bar, double T_bar, int32_t iters,
-                double tol)
+                double tol, int32_t midpoint)
 {
     if (!ctx) return DM_EINVAL;
     if (n_steps < 0 || n_steps > (1 << 30)) return fail(ctx, DM_EINVAL, "bad n_steps");
@@ -805,6 +805,7 @@ int dm_step_wlc(dm_ctx *ctx, int64_t n_steps, double dt_bar, double T_bar, int32
         int rc = bucket_positions(ctx, b, ctx->stream);  // b.d_r = phi R (FP64)
         if (rc) return rc;
         DM_HIP(ctx, dm::launch_wlc(b.d_r, b.d_wlc, b.d_ids, b.M, b.n, T_bar, dt_bar, iters, tol,
+                                   midpoint ? 1 : 0,
                                    ctx->seed, ctx->step, (int)n_steps, ctx->stream));
         DM_HIP(ctx, dm::launch_gemm_f64(b.d_Afwd, b.d_r, b.d_R64, b.M, 3 * b.n, ctx->stream));
         if (fused_precision(ctx->precision))

@@ -77,11 +77,13 @@ hipError_t launch_euler_f64(double *pos, const int32_t *ids, int M, int nch,
 // scr, which holds wlc_scratch_doubles(M, nch) doubles (0 when the chain fits
 // the LDS; scr may then be null).  The tension cycle runs at most iters
 // times and, with tol > 0, stops after a cycle that moves no bond component
-// by more than tol.
+// by more than tol.  midpoint != 0: forces and tensions act along the
+// midpoint bonds (u_n + u'_n)/|u_n + u'_n|; 0: along the bonds u_n of the
+// start of the step.
 size_t wlc_scratch_doubles(int M, int nch);
 hipError_t launch_wlc(double *pos, double *scr, const int32_t *ids, int M, int nch, double T_bar,
-                      double dt, int iters, double tol, uint64_t seed, int64_t step0,
-                      int n_steps, hipStream_t st);
+                      double dt, int iters, double tol, int midpoint, uint64_t seed,
+                      int64_t step0, int n_steps, hipStream_t st);
 
 // n_sweeps Metropolis sweeps of the FP64 amplitudes R (nch chains of 3*M),
 // with chiT[p*(M-1) + n-1] = chi_{n,p} and step half-widths sstep[p]; the

@@ -613,7 +613,8 @@ __global__ __launch_bounds__(64) void wlc_kernel(double *__restrict__ pos,
                                                  double *__restrict__ scr,
                                                  const int32_t *__restrict__ ids, int M, int nch,
                                                  double T_bar, double dt, int iters, double tol,
-                                                 uint64_t seed, int64_t step0, int n_steps)
+                                                 int midpoint, uint64_t seed, int64_t step0,
+                                                 int n_steps)
 {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= nch) return;
@@ -668,7 +669,7 @@ __global__ __launch_bounds__(64) void wlc_kernel(double *__restrict__ pos,
                     s2 += w[a] * w[a];
                 }
                 const double inv = 1.0 / sqrt(s2);
-                for (int a = 0; a < 3; ++a) V3(UM, n, a) = w[a] * inv;
+                for (int a = 0; a < 3; ++a) V3(UM, n, a) = midpoint ? w[a] * inv : V3(U, n, a);
             }
             // Thomas forward sweep: a f_{n-1} + b f_n + c f_{n+1} = r
             double cp = 0.0, dp = 0.0;
@@ -737,8 +738,8 @@ __host__ __device__ inline size_t wlc_lds_doubles(int M)
 __global__ __launch_bounds__(64) void wlc_wave_kernel(double *__restrict__ pos,
                                                       const int32_t *__restrict__ ids, int M,
                                                       double T_bar, double dt, int iters,
-                                                      double tol, uint64_t seed, int64_t step0,
-                                                      int n_steps)
+                                                      double tol, int midpoint, uint64_t seed,
+                                                      int64_t step0, int n_steps)
 {
     extern __shared__ double lds[];
     const int c = blockIdx.x, t = threadIdx.x;
@@ -784,7 +785,7 @@ __global__ __launch_bounds__(64) void wlc_wave_kernel(double *__restrict__ pos,
                     s2 += w[a] * w[a];
                 }
                 const double inv = 1.0 / sqrt(s2);
-                for (int a = 0; a < 3; ++a) UM[a * P + n] = w[a] * inv;
+                for (int a = 0; a < 3; ++a) UM[a * P + n] = midpoint ? w[a] * inv : U[a * P + n];
             }
             __syncthreads();
             for (int n = t; n <= N; n += 64)  // regular displacements of the beads
@@ -906,8 +907,8 @@ __device__ __forceinline__ double from_next(double v) { return wave_shift<kWaveS
 __global__ __launch_bounds__(256) void wlc_reg_kernel(double *__restrict__ pos,
                                                       const int32_t *__restrict__ ids, int M,
                                                       int nch, double T_bar, double dt, int iters,
-                                                      double tol, uint64_t seed, int64_t step0,
-                                                      int n_steps)
+                                                      double tol, int midpoint, uint64_t seed,
+                                                      int64_t step0, int n_steps)
 {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int c = blockIdx.x * 4 + wv;
@@ -958,7 +959,7 @@ __global__ __launch_bounds__(256) void wlc_reg_kernel(double *__restrict__ pos,
                     s2 += w[a] * w[a];
                 }
                 const double inv = bond ? 1.0 / sqrt(s2) : 0.0;
-                for (int a = 0; a < 3; ++a) UM[a] = bond ? w[a] * inv : 0.0;
+                for (int a = 0; a < 3; ++a) UM[a] = bond ? (midpoint ? w[a] * inv : U[a]) : 0.0;
             }
             double Dl[3];
             for (int a = 0; a < 3; ++a) {  // bending gradients and bead displacements
@@ -1167,25 +1168,25 @@ size_t wlc_scratch_doubles(int M, int nch)
 }
 
 hipError_t launch_wlc(double *pos, double *scr, const int32_t *ids, int M, int nch, double T_bar,
-                      double dt, int iters, double tol, uint64_t seed, int64_t step0,
-                      int n_steps, hipStream_t st)
+                      double dt, int iters, double tol, int midpoint, uint64_t seed,
+                      int64_t step0, int n_steps, hipStream_t st)
 {
     if (nch == 0 || n_steps == 0) return hipSuccess;
     if (M < 2 || iters < 1) return hipErrorInvalidValue;
     if (M <= kWlcRegMaxM) {
         hipLaunchKernelGGL(wlc_reg_kernel, dim3((nch + 3) / 4), dim3(256), 0, st, pos, ids, M, nch,
-                           T_bar, dt, iters, tol, seed, step0, n_steps);
+                           T_bar, dt, iters, tol, midpoint, seed, step0, n_steps);
         return hipGetLastError();
     }
     const size_t lds = sizeof(double) * wlc_lds_doubles(M);
     if (lds <= kWlcMaxLds) {
         hipLaunchKernelGGL(wlc_wave_kernel, dim3(nch), dim3(64), lds, st, pos, ids, M, T_bar, dt,
-                           iters, tol, seed, step0, n_steps);
+                           iters, tol, midpoint, seed, step0, n_steps);
         return hipGetLastError();
     }
     if (!scr) return hipErrorInvalidValue;
     hipLaunchKernelGGL(wlc_kernel, dim3((nch + 63) / 64), dim3(64), 0, st, pos, scr, ids, M, nch,
-                       T_bar, dt, iters, tol, seed, step0, n_steps);
+                       T_bar, dt, iters, tol, midpoint, seed, step0, n_steps);
     return hipGetLastError();
 }
 

@@ -22,19 +22,21 @@ def _device():
     torch.cuda.synchronize()
 
 
+@pytest.mark.parametrize("midpoint", [True, False])
 @pytest.mark.parametrize("M", [2, 3, 17, 64, 65, 66, 100, 341, 342])
-def test_wlc_matches_oracle(M):
+def test_wlc_matches_oracle(M, midpoint):
     """Up to M = 64 one wavefront per chain with the chain in registers (bond
     n in lane n); up to M = 341 one wavefront per chain with the chain in LDS
     (several bonds per lane from M = 66); both solve for the tensions by
     cyclic reduction.  From M = 342 one thread per chain runs the Thomas
-    sweep."""
+    sweep.  Both forms of the cycle: forces at the midpoint bonds and at
+    the bonds of the start of the step."""
     B, T, dt, n = 7, 0.2, 2e-3, 150
     pos = unit_chains(B, M, M)
     with Context(pos, seed=12, precision="fp64") as ctx:
-        ctx.step_wlc(n, dt, T, iters=8)
+        ctx.step_wlc(n, dt, T, iters=8, midpoint=midpoint)
         got = ctx.positions()
-    want = oracle.step_wlc(pos, T, dt, n, iters=8, seed=12)
+    want = oracle.step_wlc(pos, T, dt, n, iters=8, seed=12, midpoint=midpoint)
     err = np.abs(got - want).max() / max(1.0, M - 1)
     print(f"M={M}: max |dr| / (M-1) = {err:.2e}")
     assert err < 1e-10

@@ -686,27 +686,31 @@ def test_wlc_cycle_converges_to_its_fixed_point():
     assert np.abs(np.linalg.norm(np.diff(one, axis=2), axis=1) - 1).max() > 1e-6
 
 
-def test_wlc_dumbbell_rotational_diffusion():
+@pytest.mark.parametrize("midpoint", [True, False])
+def test_wlc_dumbbell_rotational_diffusion(midpoint):
     """One rigid bond between two unit-friction beads: the orientation
-    diffuses with D_r = 2 T-bar, so <u(t).u(0)> = exp(-4 T-bar t)."""
+    diffuses with D_r = 2 T-bar, so <u(t).u(0)> = exp(-4 T-bar t).  Both
+    forms of the cycle (tension along the midpoint bond, Eq. y14, or along
+    the bond of the start of the step) approach it as dt -> 0."""
     B, T, dt = 3000, 0.5, 1e-3
     x0 = _unit_chains(B, 2, 3)
     u0 = x0[:, :, 1] - x0[:, :, 0]
     x, step = x0, 0
     for t in (0.2, 0.4, 0.6):
         n = int(round(t / dt)) - step
-        x = oracle.step_wlc(x, T, dt, n, iters=6, seed=4, step0=step)
+        x = oracle.step_wlc(x, T, dt, n, iters=6, seed=4, step0=step, midpoint=midpoint)
         step += n
         c = ((x[:, :, 1] - x[:, :, 0]) * u0).sum(axis=1)
         assert c.mean() == pytest.approx(np.exp(-4 * T * t), abs=4 * c.std() / np.sqrt(B))
 
 
-def test_wlc_centre_of_mass_diffusion():
+@pytest.mark.parametrize("midpoint", [True, False])
+def test_wlc_centre_of_mass_diffusion(midpoint):
     """Internal forces cancel: the centre of mass of M unit-friction beads
     diffuses with D = T-bar / M."""
     B, M, T, dt, n = 2000, 5, 0.3, 2e-3, 500
     x0 = _unit_chains(B, M, 5)
-    x = oracle.step_wlc(x0, T, dt, n, iters=6, seed=6)
+    x = oracle.step_wlc(x0, T, dt, n, iters=6, seed=6, midpoint=midpoint)
     d2 = ((x.mean(axis=2) - x0.mean(axis=2)) ** 2).sum(axis=1)
     want = 6 * T / M * n * dt
     assert d2.mean() == pytest.approx(want, abs=4 * d2.std() / np.sqrt(B))
@@ -735,6 +739,28 @@ def test_wlc_trimer_angle_follows_the_constrained_ensemble():
     se = v.std() / np.sqrt(v.size)
     assert abs(v.mean() - rigid) < 4 * se, (v.mean(), rigid, se)
     assert abs(stiff - rigid) > 4 * se
+
+
+def test_wlc_forces_at_the_start_bond_hold_unit_bonds_and_differ_from_midpoint():
+    """The cycle with forces and tensions along the bonds of the start of the
+    step still enforces (u + u') . du = 0, so converged cycles keep unit
+    bonds; it is a different scheme from the midpoint form (their paths
+    separate at O(dt) per step), and the two agree as dt -> 0: the
+    difference after a fixed time shrinks at least linearly with dt."""
+    x0 = _unit_chains(8, 12, 21)
+    lit = oracle.step_wlc(x0, 0.1, 2e-3, 300, iters=30, seed=5, tol=1e-13, midpoint=False)
+    mid = oracle.step_wlc(x0, 0.1, 2e-3, 300, iters=30, seed=5, tol=1e-13)
+    assert np.abs(np.linalg.norm(np.diff(lit, axis=2), axis=1) - 1).max() < 1e-11
+    assert np.abs(lit - mid).max() > 1e-6
+    # same noise path at dt and dt/2 is not available (counter-based noise
+    # per step), so compare deterministic runs: T-bar tiny
+    gaps = []
+    for dt in (4e-3, 2e-3, 1e-3):
+        n = int(round(0.4 / dt))
+        a = oracle.step_wlc(x0, 1e-12, dt, n, iters=40, seed=5, tol=1e-14, midpoint=False)
+        b = oracle.step_wlc(x0, 1e-12, dt, n, iters=40, seed=5, tol=1e-14)
+        gaps.append(np.abs(a - b).max())
+    assert gaps[1] < 0.6 * gaps[0] and gaps[2] < 0.6 * gaps[1], gaps
 
 
 # ---------------------------------------------------------------- initial state
