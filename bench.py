@@ -552,7 +552,7 @@ def steps_with_progress(ctx, n, label, chunk=2_000_000):
 
 
 def dtmax_workload(args):
-    """Equilibrium values Q(0) of the mode dynamics (Sec. 6: <L^2>, middle
+    """Equilibrium values Q(0) of the mode dynamics (Sec. V.B: <L^2>, middle
     bead about the centre of mass, bond moments) for several time steps,
     each divided by its Metropolis value; the paper accepts a time step
     while all ratios stay within 5 %.  Chains are equilibrated by Monte
@@ -620,7 +620,7 @@ def dtmax_workload(args):
 
 
 def dtmax_t_workload(args):
-    """Dynamical group of the time-step test (Sec. 6): the time correlations
+    """Dynamical group of the time-step test (Sec. V.B): the time correlations
     Q(t) (end-to-end vector, middle bond: autocorrelations; middle bead about
     the centre of mass: msd) at several time steps, from Monte Carlo
     equilibrated chains.  At fixed times tau the effective decay constant

@@ -3,14 +3,14 @@
  * Langevin dynamics of semiflexible chains of Panja, Barkema & van Leeuwen,
  * "Efficient simulation of semiflexible polymers" (arXiv:1411.3487).
  *
- * Model (Sec. 2, Eqs. a1-a3): a chain of M = N+1 beads r_0..r_N with bonds
+ * Model (Sec. II, Eqs. a1-a3): a chain of M = N+1 beads r_0..r_N with bonds
  * u_n = r_n - r_{n-1}, Hamiltonian
  *     H = lambda/2 sum_n (|u_n| - d)^2 - kappa sum_n u_n . u_{n+1},
  * reduced by nu = kappa/lambda and T* = kT/(lambda d^2); lengths in units of
- * d, time in units of xi/lambda (Sec. 3, Eqs. b3-b5).  Overdamped Langevin
+ * d, time in units of xi/lambda (Sec. III, Eqs. b3-b5).  Overdamped Langevin
  * dynamics with friction xi and thermal noise of variance 2 T*.
  *
- * Method (Secs. 3a-4c): positions are expanded in Rouse modes
+ * Method (Secs. III.A–IV.B): positions are expanded in Rouse modes
  * phi_{n,p} = sqrt(2/M) cos(p (n + 1/2) pi / M) (phi_{n,0} = 1/sqrt(M)),
  * Eqs. (c1), (c8); each amplitude R_p obeys Eq. (e10),
  *     dR_p/dtau = -zeta_p R_p + Delta H_p + G_p,
@@ -76,7 +76,7 @@ extern "C" {
 #define DM_OBS_ACCUM  4  /* per length bucket, sums since the last reset */
 #define DM_OBS_RESET  8  /* zero the accumulators after copying them out */
 
-/* Per-chain observables (Sec. 5b): index into the DM_OBS_CHAIN block. */
+/* Per-chain observables (Sec. V.B): index into the DM_OBS_CHAIN block. */
 #define DM_NCHAIN_OBS   16
 #define DM_CO_BOND       0  /* mean bond length (1/N) sum_n |u_n| */
 #define DM_CO_L2         1  /* |L|^2, end-to-end vector L = r_N - r_0 */
@@ -91,13 +91,13 @@ extern "C" {
    sum over samples and chains of |R_p|^2 for p = 0..M-1, then
    DM_NTUMBLE_BINS counts of tumbling times: bin k counts intervals tau
    (in steps) with 2^k <= tau < 2^(k+1) (the last bin also everything
-   longer).  Tumbling (Sec. 7d, simple shear): the in-plane end-to-end
+   longer).  Tumbling (Sec. VIII, simple shear): the in-plane end-to-end
    vector (L_x, L_y) is "along +x" once L_x > |(L_x, L_y)|/2 and "along -x"
    once L_x < -|(L_x, L_y)|/2 (hysteresis: in between the previous state is
    kept); each change between the two states at a sample is one tumble, and
    a tumbling time is the interval between two tumbles of a chain.
    Then DM_NCORR blocks of 4 doubles, one per lag l_j (l_0 = 0,
-   l_j = 2^(j-1) samples), for the time correlations of Sec. 6 (measured
+   l_j = 2^(j-1) samples), for the time correlations of Sec. V.B (measured
    for j < corr_lags, zero otherwise): sum of L(t).L(t - l_j) (end-to-end
    vector), of u_m(t).u_m(t - l_j) (middle bond u_{M/2}), of
    |d(t) - d(t - l_j)|^2 with d = r_{(M-1)/2} - r_cm (msd of the middle bead
@@ -142,7 +142,7 @@ typedef struct dm_ctx dm_ctx;
    Physical units when lambda > 0 (pN/nm for lambda and kappa, pN nm for kT,
    nm for a, pN ps/nm for xi, ps for dt, 1/ps for gamma_dot): then
    nu = kappa/lambda, b = 1/(1-2nu), d = a/b, T* = kT/(lambda d^2) (Eqs. a2,
-   a3) and dtau = dt lambda/xi (Sec. 3).  Reduced units when lambda == 0:
+   a3) and dtau = dt lambda/xi (Sec. III).  Reduced units when lambda == 0:
    T_star, nu, dt (= dtau) and gamma_dot are used as given. */
 typedef struct {
     double lambda, kappa, kT, a, xi;
@@ -213,14 +213,14 @@ int dm_init_chains(dm_ctx **out, int32_t n_chains, const int32_t *beads,
                    const double *pos0, uint64_t seed, int32_t precision,
                    void *hip_stream);
 
-/* Set model parameters and time steps (Secs. 2, 3, 7b); builds the mode
+/* Set model parameters and time steps (Secs. II, III, VII.B); builds the mode
    tables of Eqs. (c8), (c9), (e9), (d3), (d6), (f2) in FP64 on the host for
    every chain length and uploads them.  May be called again to change
    parameters.  Errors: DM_EINVAL for nu outside [0, 1/2) (stability of
    Eq. a2), T* <= 0, dt <= 0, or a chain length missing from lengths[]. */
 int dm_set_params(dm_ctx *ctx, const dm_params *p);
 
-/* Advance every chain by n_steps mode steps (Sec. 4, Eqs. e10, d3, d6, f2):
+/* Advance every chain by n_steps mode steps (Sec. IV, Eqs. e10, d3, d6, f2):
    inverse transform of the internal modes to bond vectors, the nonlinear
    bond force g_n = u_n (1/|u_n| - (1-2nu)) (Eqs. e4, e11), forward
    transform to Delta H_p, and the per-mode update with Philox noise; the
@@ -232,11 +232,11 @@ int dm_step_modes(dm_ctx *ctx, int64_t n_steps);
    dtau (Eqs. b3-b5): r_n += dtau (h_{n+1} - h_n) + sqrt(2 T* dtau) eta_n with
    h_n = (|u_n| - 1) u_n/|u_n| - nu (u_{n-1} + u_{n+1}), in FP64.  The
    state is converted from and back to mode amplitudes once per call.
-   The scheme is unstable for dtau above about 0.3 (Sec. 3a).
+   The scheme is unstable for dtau above about 0.3 (Sec. III.A).
    Errors: DM_ESTATE, DM_EINVAL (dtau <= 0), DM_ENONFINITE (check_finite). */
 int dm_step_euler(dm_ctx *ctx, int64_t n_steps, double dtau);
 
-/* The nu -> 0 limit (Sec. 5c, Eqs. y2-y14): the inextensible wormlike chain
+/* The nu -> 0 limit (Sec. VI.A, Eqs. y2-y14): the inextensible wormlike chain
    in the bending units tau-bar = nu tau, T-bar = T* / nu, Hamiltonian
    -sum_n u_n . u_{n+1} with bonds of unit length held by tensions f_n.  The
    bonds of every chain are first scaled to unit length (positions then in
@@ -266,7 +266,7 @@ int dm_step_wlc(dm_ctx *ctx, int64_t n_steps, double dt_bar, double T_bar,
                 int32_t iters, double tol, int32_t midpoint);
 
 /* Metropolis Monte Carlo in the mode representation, the paper's benchmark
-   for equilibrium values (Sec. 6: large steps in the slow modes, small in
+   for equilibrium values (Sec. V.B: large steps in the slow modes, small in
    the fast ones).  One sweep proposes, for p = 1..M-1 and component
    a = x, y, z in order, R_p^a += delta, delta uniform on (-s_p, s_p) with
    s_p = step_scale * sqrt(T* / zeta^l_p) (the width of mode p under the
@@ -284,7 +284,7 @@ int dm_step_wlc(dm_ctx *ctx, int64_t n_steps, double dt_bar, double T_bar,
 int dm_step_mc(dm_ctx *ctx, int64_t n_sweeps, double step_scale,
                int64_t *accepted);
 
-/* Observables of Sec. 5b.  which = OR of DM_OBS_* bits; the selected blocks
+/* Observables of Sec. V.B.  which = OR of DM_OBS_* bits; the selected blocks
    are written to out_host in the order CHAIN, MODES, ACCUM (see the layout
    macros above).  out_len is the capacity in doubles; dm_observables_size()
    gives the length needed.  Synchronises the stream.
@@ -322,7 +322,7 @@ int dm_get_tiling(const dm_ctx *ctx, double *out, size_t len, int32_t *n_buckets
 /* Text of the last autotuning (one line per timed tile shape), or "". */
 const char *dm_tuning_report(const dm_ctx *ctx);
 
-/* Model parameters of a coarse-grained chain (Sec. 7): one bead per k
+/* Model parameters of a coarse-grained chain (Sec. VI): one bead per k
    basepairs, on the force-extension curve of Eq. (x1) with r = l_p / a and
    y = l_p K_0 / kT (Eq. x2).  With r_k = r / k and y unchanged, Eq. (x4):
        T*_k = (2 r^2 + k^2 y) r / (k^3 y^2),  nu_k = r^2 / (2 r^2 + k^2 y)
@@ -331,7 +331,7 @@ const char *dm_tuning_report(const dm_ctx *ctx);
    context.  Errors: DM_EINVAL for r <= 0, y <= 0, k < 1 or NULL outputs. */
 int dm_coarse_grain(double r, double y, int32_t k, double *T_star_k, double *nu_k);
 
-/* Time unit of that coarse-grained chain (Sec. 7b, Eq. g2 with a_k = k a and
+/* Time unit of that coarse-grained chain (Sec. VII.B, Eq. g2 with a_k = k a and
    the friction of k basepairs, xi_k = k xi): real time t = c_k tau_k with
        c_k = k^3 T*_k (1 - 2 nu_k)^2   [in units of a^2 xi / kT],
    a the basepair spacing and xi the friction per basepair.  Host only.

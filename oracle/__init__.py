@@ -1,8 +1,8 @@
 """FP64 CPU oracle -- TEST INFRASTRUCTURE, NOT PART OF THE PRODUCT.
 
 Plain, slow, obviously-correct reference for the mode-amplitude Langevin step
-of Panja, Barkema & van Leeuwen (arXiv:1411.3487), Secs. 2-4, and the
-bead-space Euler scheme of Sec. 3 (Eqs. b3-b5).  The arithmetic lives in
+of Panja, Barkema & van Leeuwen (arXiv:1411.3487), Secs. II–IV, and the
+bead-space Euler scheme of Sec. III (Eqs. b3-b5).  The arithmetic lives in
 ``dm_oracle.c`` (plain C, FP64, OpenMP over chains); this module only
 compiles it with gcc and marshals numpy arrays through ctypes.
 
@@ -271,7 +271,7 @@ TUMBLE_BINS = 32
 
 
 def tumbles(Lx, Ly, steps):
-    """Tumbles of one chain under simple shear (Sec. 7d) from its in-plane
+    """Tumbles of one chain under simple shear (Sec. VIII) from its in-plane
     end-to-end vector (Lx, Ly) sampled at the given steps.
 
     The paper shows tumbling without defining it; the reading used here: the

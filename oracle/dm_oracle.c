@@ -12,7 +12,7 @@
  * Philox4x32-10 independently from its publication (Salmon, Moraes, Dror &
  * Shaw, "Parallel random numbers: as easy as 1, 2, 3", SC'11).
  *
- * Units are the paper's reduced ones (Sec. 3, Eqs. b3-b5): lengths in d, time
+ * Units are the paper's reduced ones (Sec. III, Eqs. b3-b5): lengths in d, time
  * in xi/lambda, noise variance 2 T*.
  *
  * Array layout: a chain's positions or mode amplitudes are 3*M doubles,
@@ -149,14 +149,14 @@ void orc_config_chains(int M, int n_chains, const uint32_t *chain_id, double b,
 }
 
 /* ------------------------------------------------------------------------ */
-/* Model parameters, Sec. 2 (Eqs. a2, a3) and Sec. 7b (Eq. g2).             */
+/* Model parameters, Sec. II (Eqs. a2, a3) and Sec. VII.B (Eq. g2).             */
 /* ------------------------------------------------------------------------ */
 void orc_reduced_params(double lambda, double kappa, double kT, double a,
                         double xi, double *T_star, double *nu, double *b,
                         double *d, double *time_unit)
 {
     /* nu = kappa/lambda; b = 1/(1-2 nu) and a = b d (Eq. a3);
-       T* = kT/(lambda d^2); t = (xi/lambda) tau (Sec. 3). */
+       T* = kT/(lambda d^2); t = (xi/lambda) tau (Sec. III). */
     double n_ = kappa / lambda;
     double b_ = 1.0 / (1.0 - 2.0 * n_);
     double d_ = a / b_;
@@ -289,7 +289,7 @@ void orc_delta_h(int M, double nu, const double *R, double *dH)
 }
 
 /* ------------------------------------------------------------------------ */
-/* Mode step, Sec. 4: Eq. (e10) integrated with the integrating factor of   */
+/* Mode step, Sec. IV: Eq. (e10) integrated with the integrating factor of   */
 /* Eq. (d3), noise of Eq. (d6), coupling integral of Eq. (f2), and the      */
 /* shear drift of Eq. (btum).                                               */
 /* ------------------------------------------------------------------------ */
@@ -422,7 +422,7 @@ double orc_energy(int M, double nu, const double *pos)
 }
 
 /* ------------------------------------------------------------------------ */
-/* The nu -> 0 limit (Sec. 5c, Eqs. y2-y14): the inextensible wormlike      */
+/* The nu -> 0 limit (Sec. VI.A, Eqs. y2-y14): the inextensible wormlike      */
 /* chain in the bending time scale tau-bar = nu tau, T-bar = T* / nu, with   */
 /* Hamiltonian -sum_n u_n . u_{n+1} and bonds of unit length kept by the     */
 /* tensions f_n.  One step of length dt moves bead n by                      */
@@ -565,7 +565,7 @@ void orc_step_wlc(int M, int n_chains, const uint32_t *chain_id, double *pos,
 
 /* ------------------------------------------------------------------------ */
 /* Metropolis Monte Carlo in the mode representation, the paper's           */
-/* equilibrium benchmark (Sec. 6: "large MC steps in the slow modes and     */
+/* equilibrium benchmark (Sec. V.B: "large MC steps in the slow modes and     */
 /* small steps in the fast modes").  The paper gives no more detail; this   */
 /* is the reading used.  One sweep proposes, for p = 1..M-1 and component   */
 /* a = x, y, z in that order, R_p^a -> R_p^a + delta with delta uniform on  */
@@ -634,7 +634,7 @@ void orc_mc_sweeps(int M, int n_chains, const uint32_t *chain_id, double *R,
 }
 
 /* ------------------------------------------------------------------------ */
-/* Observables of Sec. 5b: per chain, from positions (3*M).                 */
+/* Observables of Sec. V.B: per chain, from positions (3*M).                 */
 /* out[0] mean bond length, out[1] |L|^2 with L = r_{M-1} - r_0,            */
 /* out[2..4] L, out[5..7] centre of mass, out[8..10] middle bond            */
 /* u_m (m = M/2), out[11..13] r_mid - r_cm (mid = (M-1)/2),                 */

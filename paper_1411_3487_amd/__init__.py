@@ -8,7 +8,7 @@ include/dnamodes.h); this package holds the build script, a ctypes binding
 from ._lib import (Context, DMError, coarse_grain, load, DM_FP64, DM_FP32, DM_BF16X3,  # noqa: F401
                    DM_OBS_CHAIN, DM_OBS_MODES, DM_OBS_ACCUM, DM_OBS_RESET)
 
-# dsDNA in the paper's reduced units (Sec. 2a) and its maximal time steps
+# dsDNA in the paper's reduced units (Sec. II.A) and its maximal time steps
 # per chain length (Table 1; 96/192/384 bp take the next shorter length's).
 NU_DSDNA = 0.35
 T_STAR_DSDNA = 0.034

@@ -12,7 +12,7 @@
 // inside the transform keeps the O(|u|) bond vectors free of the O(M |u|)
 // positions, which is what lets the transforms run in FP32 or split BF16.
 //
-// Mirror symmetry (Sec. 5a: phi_{N-n,p} = (-1)^p phi_{n,p}) gives
+// Mirror symmetry (Sec. V.A: phi_{N-n,p} = (-1)^p phi_{n,p}) gives
 // chi_{M-n,p} = (-1)^{p+1} chi_{n,p}: for half-bond rows i = 1..H (H = M/2)
 //   S_i = sum_{p odd} chi_{i,p} R_p,  A_i = sum_{p even} chi_{i,p} R_p,
 //   u_i = S_i + A_i,  u_{M-i} = S_i - A_i,
@@ -1032,7 +1032,7 @@ __device__ __forceinline__ size_t state_slot(int j, int alpha, int p, int RT)
 // Observables of the fused state, one workgroup of 4 wavefronts per tile.  Positions
 // relative to the centre of mass, r_n - r_cm = sum_{p >= 1} phi_{n,p} R_p
 // (Eq. c1; the internal modes sum to zero over the beads), in the mirror
-// halves of Sec. 5a (the 4 wavefronts share the row tiles): for beads n < H
+// halves of Sec. V.A (the 4 wavefronts share the row tiles): for beads n < H
 //   O_n = sum_{p odd} phi_{n,p} R_p,  E_n = sum_{p even} phi_{n,p} R_p,
 //   r_n = E_n + O_n,  r_{M-1-n} = E_n - O_n,
 // as FP32 MFMA products with the tables P (odd: phi_{n,2j+1}; even:

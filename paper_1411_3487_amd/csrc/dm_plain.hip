@@ -399,7 +399,7 @@ __global__ __launch_bounds__(1024) void euler_f64_kernel(double *__restrict__ po
 }
 
 // --------------------------------------------------------------------------
-// Observables (Sec. 5b): one wave per chain, FP64 wavefront reductions.
+// Observables (Sec. V.B): one wave per chain, FP64 wavefront reductions.
 // --------------------------------------------------------------------------
 __device__ __forceinline__ double wave_sum(double v)
 {
@@ -523,7 +523,7 @@ __global__ __launch_bounds__(64) void chain_obs_kernel(const double *__restrict_
 }
 
 // Metropolis Monte Carlo in the mode representation, one wavefront per
-// chain (the paper's equilibrium benchmark, Sec. 6).  A sweep proposes, for
+// chain (the paper's equilibrium benchmark, Sec. V.B).  A sweep proposes, for
 // p = 1..M-1 and component a = x, y, z in order, R_p^a += delta with delta
 // uniform on (-s_p, s_p), and accepts with probability
 // min(1, exp(-dH'/T*)) for the reduced Hamiltonian of Eq. (b3).  The bond
@@ -596,7 +596,7 @@ __global__ __launch_bounds__(64) void mc_kernel(double *__restrict__ R,
     if (lane == 0) accepted[c] = acc;
 }
 
-// The nu -> 0 limit (Sec. 5c, Eqs. y2-y14), one thread per chain, FP64: the
+// The nu -> 0 limit (Sec. VI.A, Eqs. y2-y14), one thread per chain, FP64: the
 // inextensible chain in bending units (tau-bar, T-bar), bonds of unit
 // length held by tensions.  A step moves bead n by
 //   dr_n = (-f_n u^m_n + f_{n+1} u^m_{n+1} + h_{n+1} - h_n) dt + sqrt(2 T-bar dt) eta_n,

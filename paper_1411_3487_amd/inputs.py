@@ -5,7 +5,7 @@ conformations and chain lengths with numpy's default generator, so that the
 HIP library and the CPU oracle can be started from identical inputs.
 
 Recipe (the paper's workloads are single dsDNA chains of 64-512 basepairs,
-one bead per basepair, Sec. 2a and Sec. 5b):
+one bead per basepair, Sec. II.A and Sec. V.B):
   * a chain of M beads starts straight, with consecutive beads ``spacing``
     apart (the mean bond length a = b d, i.e. b in reduced units), along x
     or along a direction drawn uniformly on the unit sphere;

@@ -85,12 +85,12 @@ def test_coarse_grain_reproduces_table3():
 
 
 def test_coarse_grain_time_unit_reproduces_table5():
-    """Sec. 7b, Table 5: t = c_k tau under coarse-graining by k.  The ratios
+    """Sec. VII.B, Table 5: t = c_k tau under coarse-graining by k.  The ratios
     c_k / c_1 follow from Table 3's parameters with a_k = k a and xi_k = k xi
     (Eq. g2) to the printed digits.  The absolute scale: c_1 = 1.54 ps in the
     table is 10x the unit behind Table 2 (c_1 = T*/b^2 a^2 xi/kT = 0.153 ps
     with a^2 xi/kT = 52.0 ps, so that dtau = 10, 50, 100 give its 1.59, 7.96,
-    15.9 ps), the same factor as the prose time unit of Sec. 7b."""
+    15.9 ps), the same factor as the prose time unit of Sec. VII.B."""
     rows = np.loadtxt(os.path.join(ROOT, "tests", "golden", "table5_time_units.txt"))
     c1 = _lib.coarse_grain_time(120.0, 12000.0, 1)
     for k, ck in rows:

@@ -1,4 +1,4 @@
-"""Time correlations of Sec. 6 in the accumulators (corr_lags).
+"""Time correlations of Sec. V.B in the accumulators (corr_lags).
 
 Per lag l_j (0, 1, 2, 4, ... samples) the sums over chains and sample pairs
 (t, t - l_j) of L(t).L(t - l_j), u_m(t).u_m(t - l_j) and

@@ -66,7 +66,7 @@ def test_mc_on_fused_contexts(prec):
 
 
 def test_mc_equilibrium_values_match_mode_dynamics():
-    """Q(0) of Sec. 6 for 32-bead chains: <L^2>, <|u_mid|^2> and
+    """Q(0) of Sec. V.B for 32-bead chains: <L^2>, <|u_mid|^2> and
     <|r_mid - r_cm|^2> from the sampler and from FP64 mode dynamics at
     dtau = 1 (well below the time steps of Table 1), within 5 %."""
     B, M = 256, 32
@@ -91,7 +91,7 @@ def test_mc_equilibrium_values_match_mode_dynamics():
 
 
 def test_coarse_grained_chain_keeps_the_end_to_end_distance():
-    """Sec. 7: a 128-bp chain as 129 beads (k = 1) or as 65 beads of two
+    """Sec. VI: a 128-bp chain as 129 beads (k = 1) or as 65 beads of two
     basepairs (k = 2) with the parameters of Eq. (x4) (r = 120, y = 12000):
     Monte Carlo <L^2> in units of a^2 agree within 5 %, and both lie within
     10 % of the wormlike-chain value 2 l_p L_c [1 - (l_p/L_c)(1 - e^{-L_c/l_p})]."""

@@ -224,7 +224,7 @@ def test_invalid_parameters_are_rejected():
 
 
 def test_unstable_euler_reports_nonfinite_state():
-    """Sec. 3a: Euler blows up above dtau ~ 0.3; the finite check reports it."""
+    """Sec. III.A: Euler blows up above dtau ~ 0.3; the finite check reports it."""
     pos = inputs.straight_chains(2, 32, B_FAC, seed=3)
     with Context(pos, seed=0, precision="fp64") as ctx:
         ctx.set_params([32], [1.0], T_star=TS, nu=NU, check_finite=True)

@@ -17,8 +17,8 @@ import scipy.stats
 
 import oracle
 
-NU = 0.35        # dsDNA, Sec. 2a
-TSTAR = 0.034    # dsDNA, Sec. 2a
+NU = 0.35        # dsDNA, Sec. II.A
+TSTAR = 0.034    # dsDNA, Sec. II.A
 B_FAC = 1.0 / (1.0 - 2.0 * NU)   # Eq. (a3)
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -166,10 +166,10 @@ def test_step_coefficients_by_quadrature(M, dtau):
 
 def test_time_step_table_in_physical_units():
     """Table 2: dtau_max 10/50/100/100 <-> dt_max 1.59/7.96/15.9/15.9 ps,
-    via Eq. (g2) with a^2 xi / kT = 52.0 ps (Sec. 7b)."""
+    via Eq. (g2) with a^2 xi / kT = 52.0 ps (Sec. VII.B)."""
     rows = np.loadtxt(os.path.join(HERE, "golden", "table2_time_steps.txt"))
-    kT = 4.089                       # pN nm at 23 C (Sec. 7b)
-    a = 0.33                         # nm (Sec. 2a)
+    kT = 4.089                       # pN nm at 23 C (Sec. VII.B)
+    a = 0.33                         # nm (Sec. II.A)
     xi = 52.0 * kT / a ** 2          # pN ps / nm, so that a^2 xi/kT = 52.0 ps
     d = a / B_FAC
     lam = kT / (TSTAR * d * d)
@@ -224,7 +224,7 @@ def test_bead_force_is_energy_gradient(M):
 
 # ---------------------------------------------------------------- dynamics
 def test_free_mode_step_is_exact_ou_transition():
-    """With the coupling off each mode is an OU process (Sec. 4, Eqs. d3, d6):
+    """With the coupling off each mode is an OU process (Sec. IV, Eqs. d3, d6):
     one step from a fixed state has mean E_p R_p and variance W_p^2."""
     M, B, dtau = 8, 6000, 3.0
     R0 = np.tile(near_straight(M, 1), (1, 1))
@@ -241,7 +241,7 @@ def test_free_mode_step_is_exact_ou_transition():
 
 
 def test_centre_of_mass_diffuses_with_D_equal_T_over_M():
-    """Sec. 7b: free-draining D = kT/(M xi), i.e. T*/M in reduced units;
+    """Sec. VII.B: free-draining D = kT/(M xi), i.e. T*/M in reduced units;
     <|dr_cm|^2> = 6 D tau for any dtau because Delta H_0 = 0."""
     M, B, dtau, K = 16, 800, 5.0, 40
     pos = np.stack([near_straight(M, s) for s in range(B)])
@@ -292,7 +292,7 @@ def test_mode_step_is_first_order_consistent_with_ode():
 
 
 def test_euler_linear_stability_limit():
-    """Sec. 3a: Euler is unstable near dtau = 0.3; the linear bound is
+    """Sec. III.A: Euler is unstable near dtau = 0.3; the linear bound is
     2 / max zeta^l = 1 / (2 (1 + 2 nu)) ~ 0.294 for nu = 0.35.  Below it the
     noise-free iteration relaxes to the ground state; just above it the
     zig-zag mode no longer decays; well above it the chain blows up."""
@@ -474,7 +474,7 @@ def test_euler_shear_drift_from_ground_state():
 
 
 def test_chain_observables_of_a_straight_chain():
-    """Observables of Sec. 5b on a straight chain, where all are closed form."""
+    """Observables of Sec. V.B on a straight chain, where all are closed form."""
     M, s = 9, 2.5
     e = np.array([0.6, 0.0, 0.8])
     pos = e[:, None] * (np.arange(M) * s)[None, :] + np.array([1.0, -2.0, 3.0])[:, None]
