@@ -63,7 +63,9 @@ def parse():
                     choices=["auto", "resident", "streamed", "split"],
                     help="force a tile shape of the fused launch where it exists (modes and "
                          "uneven workloads; overrides the autotuner)")
-    ap.add_argument("--fp64-steps", type=int, default=500)
+    ap.add_argument("--fp64-steps", type=int, default=0,
+                    help="steps of the FP64 plain-form leg (0: the same window as the timed "
+                         "mixed-precision steps)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1024,
                     help="chains in the oracle's timed sample")
@@ -193,9 +195,10 @@ def uneven_workload(args):
     finite = bool(np.all(np.isfinite(ctx.chain_observables())))
     ctx.close()
     c64 = Context(chains, seed=2, precision="fp64", stream=stream)
-    c64.set_params(LENGTHS, dts, T_star=T_STAR_DSDNA, nu=NU_DSDNA, sample_every=args.sample_every)
-    c64.step_modes(10)
-    t64 = time_steps(c64, torch, 200, stream)
+    c64.set_params(LENGTHS, dts, T_star=T_STAR_DSDNA, nu=NU_DSDNA, sample_every=args.sample_every,
+                   use_graphs=not args.no_graphs)
+    c64.step_modes(args.sample_every)
+    t64 = time_steps(c64, torch, 2 * args.sample_every, stream)
     c64.close()
     rate = B * steps / wall
     out = {
@@ -209,8 +212,8 @@ def uneven_workload(args):
                    "graphs": not args.no_graphs, "autotune": not args.no_autotune,
                    "table_mode": args.table_mode},
         "bead_steps_per_s": rate * float(np.mean(beads)),
-        "fp64_plain_chain_steps_per_s": B * 200 / t64,
-        "speedup_vs_fp64_plain": rate / (B * 200 / t64),
+        "fp64_plain_chain_steps_per_s": B * 2 * args.sample_every / t64,
+        "speedup_vs_fp64_plain": rate / (B * 2 * args.sample_every / t64),
         "state_finite": finite,
         "tiling": [{k: (float(v) if k == "item_us" else int(v)) for k, v in t.items()}
                    for t in tiling],
@@ -331,8 +334,9 @@ def stats_workload(args):
 
 def fp64_workload(args):
     """The FP64 plain form alone on the default workload (--chains x --beads,
-    --dtau), --steps timed steps with HIP events after --warmup: the
-    denominator of the mixed-precision speed-up, for profiling its kernels."""
+    --dtau), --steps timed steps (whole sampling blocks, replayed as graphs
+    unless --no-graphs) with HIP events after --warmup: the denominator of
+    the mixed-precision speed-up, for profiling its kernels."""
     import numpy as np
     import torch
     from paper_1411_3487_amd import Context, inputs, NU_DSDNA, T_STAR_DSDNA
@@ -341,16 +345,20 @@ def fp64_workload(args):
     b = 1.0 / (1.0 - 2.0 * NU_DSDNA)
     B, M = args.chains, args.beads
     pos = inputs.straight_chains(B, M, b, seed=1, random_orientation=True)
+    se = args.sample_every
+    steps = -(-args.steps // se) * se if se > 0 else args.steps
     with Context(pos, seed=1, precision="fp64", stream=stream) as c64:
-        c64.set_params([M], [args.dtau], T_star=T_STAR_DSDNA, nu=NU_DSDNA, sample_every=0)
-        c64.step_modes(args.warmup)
-        sec = time_steps(c64, torch, args.steps, stream)
+        c64.set_params([M], [args.dtau], T_star=T_STAR_DSDNA, nu=NU_DSDNA, sample_every=se,
+                       use_graphs=not args.no_graphs)
+        c64.step_modes(-(-args.warmup // se) * se if se > 0 else args.warmup)
+        sec = time_steps(c64, torch, steps, stream)
         finite = bool(np.all(np.isfinite(c64.modes())))
-    print(json.dumps({"metric": "chain-steps/s, FP64 plain form", "value": B * args.steps / sec,
-                      "unit": "chain-steps/s", "us_per_step": sec / args.steps * 1e6,
+    print(json.dumps({"metric": "chain-steps/s, FP64 plain form", "value": B * steps / sec,
+                      "unit": "chain-steps/s", "us_per_step": sec / steps * 1e6,
                       "state_finite": finite,
                       "config": {"workload": f"{B} chains x {M} bp, dtau {args.dtau:g}, "
-                                             f"{args.steps} steps, no observables"}}))
+                                             f"{steps} steps, observables every {se} steps",
+                                 "graphs": not args.no_graphs}}))
 
 
 def coarse_workload(args):
@@ -914,8 +922,9 @@ def main():
     # ---- FP64 plain form on the same GPU and workload, over the same kind
     # of window: whole sampling blocks from a block boundary
     c64 = Context(None, seed=1, precision="fp64", stream=stream, beads=beads)
-    c64.set_params([M], [args.dtau], T_star=T_STAR_DSDNA, nu=NU_DSDNA, sample_every=se)
-    fp64_steps = blocks(args.fp64_steps)
+    c64.set_params([M], [args.dtau], T_star=T_STAR_DSDNA, nu=NU_DSDNA, sample_every=se,
+                   use_graphs=not args.no_graphs)
+    fp64_steps = steps if args.fp64_steps <= 0 else blocks(args.fp64_steps)
     c64.step_modes(blocks(20))
     t64 = time_steps(c64, torch, fp64_steps, stream)
     c64.close()

@@ -162,10 +162,12 @@ typedef struct {
                                 copy of the state and keeps the combination
                                 with the shortest schedule (see
                                 dm_get_tiling); 0: fixed shapes */
-    int32_t use_graphs;      /* fused paths with sample_every > 0, 1: whole
-                                sampling blocks (the fused launch, the step
-                                counter and the observables) are captured
-                                once as a HIP graph and replayed.  When the
+    int32_t use_graphs;      /* sample_every > 0 (at most 256 on DM_FP64), 1:
+                                whole sampling blocks (the fused launch, or
+                                the FP64 plain form's four launches per step
+                                and length, the step counter and the
+                                observables) are captured once as a HIP graph
+                                and replayed.  On the fused paths, when the
                                 launch leaves compute units idle, runs of
                                 several blocks take each block's sample from
                                 a snapshot of its state on a second stream

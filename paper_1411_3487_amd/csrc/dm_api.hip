@@ -20,6 +20,10 @@ namespace {
 
 thread_local std::string g_init_error;
 
+// Longest sampling block the FP64 plain form replays as a graph (it holds
+// four kernel nodes per step and length bucket).
+constexpr int kMaxPlainGraphSteps = 256;
+
 struct Bucket {
     int M = 0;
     int n = 0;                       // chains
@@ -307,6 +311,23 @@ int capture_overlap(dm_ctx *ctx, int steps)
     return DM_OK;
 }
 
+// One FP64 plain-form mode step of one bucket on stream st at Philox step
+// k, or (step_dev non-null, inside a captured block) *step_dev + k.
+int plain_step(dm_ctx *ctx, Bucket &b, int64_t k, hipStream_t st,
+               const int64_t *step_dev = nullptr)
+{
+    const int ncol = 3 * b.n;
+    if (ctx->nonlinear) {
+        DM_HIP(ctx, dm::launch_gemm_f64(b.d_Ainv, b.d_R64, b.d_r, b.M, ncol, st));
+        DM_HIP(ctx, dm::launch_stencil_f64(b.d_r, b.d_F, b.M, b.n, 1.0 - 2.0 * ctx->nu, st));
+        DM_HIP(ctx, dm::launch_gemm_f64(b.d_Afwd, b.d_F, b.d_dH, b.M, ncol, st));
+    }
+    DM_HIP(ctx, dm::launch_mode_update_f64(b.d_R64, b.d_dH, b.d_E, b.d_C, b.d_W, b.d_ids, b.M,
+                                           b.n, ctx->seed, step_dev, k,
+                                           ctx->gamma_dot * b.dtau, ctx->nonlinear, st));
+    return DM_OK;
+}
+
 // Capture one sampling block of `steps` fused steps: the launch reads its
 // Philox step from ctx->d_step, a one-thread kernel advances it, then the
 // observables are accumulated.  No memset nodes (plain kernels only).
@@ -316,10 +337,21 @@ int capture_block(dm_ctx *ctx, int steps)
     if (!ctx->cap_stream)
         DM_HIP(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
     DM_HIP(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
-    hipError_t e = dm::fused_launch(ctx->plan, ctx->seed, 0, ctx->d_step, steps, ctx->nonlinear,
-                                    ctx->cap_stream);
-    if (e == hipSuccess) e = dm::fused_advance_step(ctx->d_step, steps, ctx->cap_stream);
-    int rc = e == hipSuccess ? observe(ctx, 1, ctx->cap_stream, true) : DM_OK;
+    hipError_t e = hipSuccess;
+    int rc = DM_OK;
+    if (fused_precision(ctx->precision)) {
+        e = dm::fused_launch(ctx->plan, ctx->seed, 0, ctx->d_step, steps, ctx->nonlinear,
+                             ctx->cap_stream);
+    } else {
+        // the plain form's four launches per step and bucket, each update
+        // reading its Philox step from the device counter
+        for (int s = 0; s < steps && rc == DM_OK; ++s)
+            for (Bucket &b : ctx->buckets)
+                if (rc == DM_OK) rc = plain_step(ctx, b, s, ctx->cap_stream, ctx->d_step);
+    }
+    if (e == hipSuccess && rc == DM_OK)
+        e = dm::fused_advance_step(ctx->d_step, steps, ctx->cap_stream);
+    if (e == hipSuccess && rc == DM_OK) rc = observe(ctx, 1, ctx->cap_stream, true);
     hipGraph_t g = nullptr;
     const hipError_t ec = hipStreamEndCapture(ctx->cap_stream, &g);
     if (e != hipSuccess || rc != DM_OK || ec != hipSuccess) {
@@ -421,22 +453,6 @@ int config_state(dm_ctx *ctx, double nu)
         DM_HIP(ctx, hipStreamSynchronize(ctx->stream));  // the host arrays die here
     }
     ctx->pending_init = false;
-    return DM_OK;
-}
-
-// One FP64 plain-form mode step of one bucket at Philox step k.
-int plain_step(dm_ctx *ctx, Bucket &b, int64_t k)
-{
-    hipStream_t st = ctx->stream;
-    const int ncol = 3 * b.n;
-    if (ctx->nonlinear) {
-        DM_HIP(ctx, dm::launch_gemm_f64(b.d_Ainv, b.d_R64, b.d_r, b.M, ncol, st));
-        DM_HIP(ctx, dm::launch_stencil_f64(b.d_r, b.d_F, b.M, b.n, 1.0 - 2.0 * ctx->nu, st));
-        DM_HIP(ctx, dm::launch_gemm_f64(b.d_Afwd, b.d_F, b.d_dH, b.M, ncol, st));
-    }
-    DM_HIP(ctx, dm::launch_mode_update_f64(b.d_R64, b.d_dH, b.d_E, b.d_C, b.d_W, b.d_ids, b.M,
-                                           b.n, ctx->seed, nullptr, k,
-                                           ctx->gamma_dot * b.dtau, ctx->nonlinear, st));
     return DM_OK;
 }
 
@@ -694,13 +710,17 @@ int dm_step_modes(dm_ctx *ctx, int64_t n_steps)
     if (!ctx->have_params) return fail(ctx, DM_ESTATE, "dm_set_params has not been called");
     if (n_steps < 0) return fail(ctx, DM_EINVAL, "n_steps must be >= 0");
     int64_t done = 0;
-    const bool graphs = fused_precision(ctx->precision) && ctx->use_graphs && ctx->sample_every > 0;
+    const bool fused = fused_precision(ctx->precision);
+    // the plain form captures its launches one by one: blocks of at most
+    // kMaxPlainGraphSteps steps
+    const bool graphs = ctx->use_graphs && ctx->sample_every > 0 &&
+                        (fused || ctx->sample_every <= kMaxPlainGraphSteps);
     while (done < n_steps) {
         const int se = ctx->sample_every;
         if (graphs && ctx->step % se == 0 && n_steps - done >= se) {
             const int64_t blocks = (n_steps - done) / se;
             bool overlap = false;
-            if (blocks >= 2) {
+            if (blocks >= 2 && fused) {
                 int rc = overlap_pays(ctx, se, &overlap);
                 if (rc) return rc;
             }
@@ -746,7 +766,7 @@ int dm_step_modes(dm_ctx *ctx, int64_t n_steps)
         } else {
             for (int64_t s = 0; s < chunk; ++s)
                 for (Bucket &b : ctx->buckets) {
-                    int rc = plain_step(ctx, b, ctx->step + s);
+                    int rc = plain_step(ctx, b, ctx->step + s, ctx->stream);
                     if (rc) return rc;
                 }
         }

@@ -232,7 +232,11 @@ __global__ __launch_bounds__(256) void stencil_f64_kernel(const double *__restri
 }
 
 // --------------------------------------------------------------------------
-// Mode update (Eqs. d3, d6, f2, btum), one thread per (chain, 4 modes).
+// Mode update (Eqs. d3, d6, f2, btum), one thread per (chain, 4 modes): its
+// three Philox blocks (one per component) give all twelve normals, and for
+// even M each row's quad moves as two 16-byte pieces, so the lanes of a
+// wavefront read and write contiguous runs and the shear drift is folded
+// into the one store.
 // --------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void mode_update_f64_kernel(
     double *__restrict__ R, const double *__restrict__ dH, const double *__restrict__ E,
@@ -252,69 +256,61 @@ __global__ __launch_bounds__(256) void mode_update_f64_kernel(
         normals4_f64(noise_bits(seed, (uint32_t)q, chain, k, (uint32_t)a, kTagMode), z[a]);
     double *Rc = R + (size_t)c * 3 * M;
     const double *dHc = dH + (size_t)c * 3 * M;
+    // a whole quad of an even-length chain moves as two 16-byte pieces per row
+    const bool vec = (M % 2 == 0) && (4 * q + 3 < M);
+    double r[3][4], d[3][4], e[4], w[4], cc[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int p = min(4 * q + j, M - 1);
+        e[j] = E[p];
+        w[j] = W[p];
+        cc[j] = C[p];
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (vec) {
+            const f64x2 *src = reinterpret_cast<const f64x2 *>(Rc + a * M + 4 * q);
+            const f64x2 lo = src[0], hi = src[1];
+            r[a][0] = lo[0], r[a][1] = lo[1], r[a][2] = hi[0], r[a][3] = hi[1];
+            if (nonlinear) {
+                const f64x2 *hs = reinterpret_cast<const f64x2 *>(dHc + a * M + 4 * q);
+                const f64x2 dl = hs[0], dh = hs[1];
+                d[a][0] = dl[0], d[a][1] = dl[1], d[a][2] = dh[0], d[a][3] = dh[1];
+            } else {
+                d[a][0] = d[a][1] = d[a][2] = d[a][3] = 0.0;
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int p = min(4 * q + j, M - 1);
+                r[a][j] = Rc[a * M + p];
+                d[a][j] = nonlinear ? dHc[a * M + p] : 0.0;
+            }
+        }
+    }
+    double v[3][4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const int p = 4 * q + j;
-        if (p >= M) break;
-        const double ry = Rc[M + p];
-        const double e = E[p], w = W[p], cc = C[p];
-        double v[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            v[a] = e * Rc[a * M + p] + w * z[a][j];
-            if (nonlinear && p > 0) v[a] += cc * dHc[a * M + p];
+            v[a][j] = e[j] * r[a][j] + w[j] * z[a][j];
+            if (nonlinear && p > 0) v[a][j] += cc[j] * d[a][j];
         }
-        v[0] += gdt * e * ry;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) Rc[a * M + p] = v[a];
-    }
-}
-
-// The same update for even M with 16-byte accesses: one thread per (chain,
-// mode pair h), modes 2h and 2h+1 of all three components, so the lanes of a
-// wavefront read and write 1 KB contiguous runs of every row and the shear
-// term is folded into the one store.  The pair's normals are the two of its
-// Box-Muller pair in Philox block h/2 (the neighbouring thread draws the same
-// block for the other pair), the same numbers as above.
-__global__ __launch_bounds__(256) void mode_update_f64_pair_kernel(
-    double *__restrict__ R, const double *__restrict__ dH, const double *__restrict__ E,
-    const double *__restrict__ C, const double *__restrict__ W,
-    const int32_t *__restrict__ ids, int M, int nch, uint64_t seed,
-    const int64_t *__restrict__ step_dev, int64_t step_off, double gdt, int nonlinear)
-{
-    const int H = M / 2;
-    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (size_t)nch * H) return;
-    const int c = (int)(idx / H), h = (int)(idx % H);
-    const int64_t k = (step_dev ? *step_dev : 0) + step_off;
-    const uint32_t chain = (uint32_t)ids[c];
-    const f64x2 e = reinterpret_cast<const f64x2 *>(E)[h];
-    const f64x2 w = reinterpret_cast<const f64x2 *>(W)[h];
-    const f64x2 cc = reinterpret_cast<const f64x2 *>(C)[h];
-    f64x2 *Rc = reinterpret_cast<f64x2 *>(R + (size_t)c * 3 * M) + h;
-    const f64x2 *dHc = reinterpret_cast<const f64x2 *>(dH + (size_t)c * 3 * M) + h;
-    f64x2 r[3], d[3], v[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        r[a] = Rc[a * H];
-        d[a] = nonlinear ? dHc[a * H] : f64x2{0.0, 0.0};
+        v[0][j] += gdt * e[j] * r[1][j];
     }
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        double z[2];
-        normal_pair_f64(noise_bits(seed, (uint32_t)(h >> 1), chain, k, (uint32_t)a, kTagMode),
-                        h & 1, z);
+        if (vec) {
+            f64x2 *dst = reinterpret_cast<f64x2 *>(Rc + a * M + 4 * q);
+            dst[0] = f64x2{v[a][0], v[a][1]};
+            dst[1] = f64x2{v[a][2], v[a][3]};
+        } else {
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            double x = e[j] * r[a][j] + w[j] * z[j];
-            if (nonlinear && 2 * h + j > 0) x += cc[j] * d[a][j];
-            v[a][j] = x;
+            for (int j = 0; j < 4; ++j)
+                if (4 * q + j < M) Rc[a * M + 4 * q + j] = v[a][j];
         }
     }
-#pragma unroll
-    for (int j = 0; j < 2; ++j) v[0][j] += gdt * e[j] * r[1][j];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) Rc[a * H] = v[a];
 }
 
 // --------------------------------------------------------------------------
@@ -1130,14 +1126,6 @@ hipError_t launch_mode_update_f64(double *R, const double *dH, const double *E, 
                                   uint64_t seed, const int64_t *step_dev, int64_t step_off,
                                   double gdt, int nonlinear, hipStream_t st)
 {
-    if (M % 2 == 0) {
-        const size_t n = (size_t)nch * (M / 2);
-        if (n == 0) return hipSuccess;
-        hipLaunchKernelGGL(mode_update_f64_pair_kernel, dim3(blocks_for(n, 256)), dim3(256), 0,
-                           st, R, dH, E, C, W, ids, M, nch, seed, step_dev, step_off, gdt,
-                           nonlinear);
-        return hipGetLastError();
-    }
     const size_t n = (size_t)nch * ((M + 3) / 4);
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(mode_update_f64_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, R,

@@ -210,3 +210,30 @@ def test_table_mode_split_where_it_exists_and_bad_modes_rejected():
         assert all(int(t["tpw"]) == 1 and int(t["resident"]) == 0 for t in til if t["split"])
         ctx.step_modes(3)
         assert np.all(np.isfinite(ctx.chain_observables()))
+
+
+def test_fp64_graph_replays_match_eager_steps():
+    """The FP64 plain form's sampling blocks replayed as a HIP graph (each
+    update reading its Philox step from the device counter) give the same
+    bits as eager steps, with eager work and synchronisations between the
+    replays, for two length buckets."""
+    beads = [64, 96, 64, 96, 96]
+    chains = [inputs.straight_chains(1, m, B_FAC, seed=60 + i)[0] for i, m in enumerate(beads)]
+    out = {}
+    for graphs in (False, True):
+        with Context(chains, seed=6, precision="fp64") as ctx:
+            ctx.set_params([64, 96], [10.0, 10.0], T_star=TS, nu=NU, sample_every=25,
+                           use_graphs=graphs)
+            ctx.step_modes(100)          # 4 replayed blocks
+            torch.cuda.synchronize()
+            ctx.step_modes(7)            # eager, partial block
+            ctx.step_modes(18)           # completes the block eagerly
+            ctx.step_modes(75)           # 3 more replays
+            out[graphs] = (ctx.modes(), ctx.accumulators())
+    for c in range(len(beads)):
+        assert np.array_equal(out[True][0][c], out[False][0][c]), c
+    for a, b in zip(out[True][1], out[False][1]):
+        assert a["n_samples"] == b["n_samples"] == 8
+        for k in ("bond", "L2", "dmid2", "msd_cm"):
+            assert a[k] == b[k], k
+        assert np.array_equal(a["modes"], b["modes"])
