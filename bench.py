@@ -88,17 +88,29 @@ def time_steps(ctx, torch, n, stream):
     return e0.elapsed_time(e1) * 1e-3
 
 
+# the sources the fused kernel is compiled from
+FUSED_SOURCES = ("dm_fused.hip", "dm_fused.h", "dm_rng.h")
+
+
+def fused_source_sha256():
+    """SHA-256 of the fused kernel's sources, concatenated in FUSED_SOURCES order."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in FUSED_SOURCES:
+        with open(os.path.join(ROOT, "paper_1411_3487_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
 def measured_traffic(precision, B, M):
     """HBM bytes per fused launch from the committed rocprofv3 FETCH_SIZE /
-    WRITE_SIZE passes, or None if the kernel source changed since."""
-    import hashlib
+    WRITE_SIZE passes, or None if the kernel's sources changed since."""
     path = os.path.join(ROOT, "profiles", "fused_kernel_traffic.json")
-    src = os.path.join(ROOT, "paper_1411_3487_amd", "csrc", "dm_fused.hip")
     try:
         rec = json.load(open(path))
     except (OSError, ValueError):
         return None
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    sha = fused_source_sha256()
     key = f"{precision}-{B}x{M}"
     if rec.get("source_sha256") != sha or key not in rec.get("workloads", {}):
         return None

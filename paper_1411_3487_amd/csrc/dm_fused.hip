@@ -147,21 +147,24 @@ __device__ __forceinline__ f32x4 mfma_f32(float a, float b, f32x4 c)
 // Bond force of the half-bond rows of one 16-row tile: G+ = g_i + g_{M-i},
 // G- = g_i - g_{M-i}, g = u (1/|u| - lin).  No masks are needed: padding rows,
 // padding columns and the antisymmetric part of the middle bond are exactly
-// zero (u = 0 gives g = 0 thanks to the tiny offset under the rsqrt), and the
+// zero (u = 0 gives g = 0 thanks to a tiny offset under the rsqrt), and the
 // middle bond, which enters G+ twice, has its coupling column halved in the
 // table.
 __device__ __forceinline__ void bond_forces(const f32x4 aS, const f32x4 aA, int alpha, float lin,
                                             f32x4 &Gp, f32x4 &Gm)
 {
+    // each component lane adds a third of the offset to its square, so the
+    // sum over the chain's three lanes carries it once
+    constexpr float kTiny3 = 1e-30f / 3.0f;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const float up = aS[r] + aA[r], um = aS[r] - aA[r];
-        const float sp = comp_sum(up * up, alpha);
-        const float sm = comp_sum(um * um, alpha);
-        const float gp = up * (__builtin_amdgcn_rsqf(sp + 1e-30f) - lin);
-        const float gm = um * (__builtin_amdgcn_rsqf(sm + 1e-30f) - lin);
-        Gp[r] = gp + gm;
-        Gm[r] = gp - gm;
+        const float sp = comp_sum(__builtin_fmaf(up, up, kTiny3), alpha);
+        const float sm = comp_sum(__builtin_fmaf(um, um, kTiny3), alpha);
+        const float tp = __builtin_amdgcn_rsqf(sp) - lin;
+        const float gm = um * (__builtin_amdgcn_rsqf(sm) - lin);
+        Gp[r] = __builtin_fmaf(up, tp, gm);
+        Gm[r] = __builtin_fmaf(up, tp, -gm);
     }
 }
 
@@ -235,6 +238,76 @@ __device__ __forceinline__ uint32_t after(uint32_t x, float d)
 // E_p R_p + W_p eta_p (+ shear), so their coupling product is the new
 // amplitude; the even ones add sigma^2 C times their product.
 constexpr int kTableFrags = 152;  // LDS for transform tables, in 1 KB fragments
+
+// u = chi R and the bond forces of a tile whose tables are resident in LDS
+// (split BF16), row tile by row tile: the 24 products of half-bond row tile I
+// run over the K slabs in order, so every accumulator sees the products in
+// the order of the stage-by-stage form (same bits); the fragments of row
+// tile I are read from LDS two K slabs ahead, and the bond forces of row
+// tile I - 1 (and the split of a finished pair) are computed between its
+// products, where the VALU work issues beside the matrix cores.
+template <int RT>
+__device__ __forceinline__ void chi_forces_resident(const f32x4 *xb, int lane, const f32x4 (&Ro)[RT],
+                                                    const f32x4 (&Re)[RT], int alpha, float lin,
+                                                    f32x4 (&Gp)[RT], f32x4 (&Gm)[RT],
+                                                    bf16x8 (&gph)[RT / 2], bf16x8 (&gpl)[RT / 2],
+                                                    bf16x8 (&gmh)[RT / 2], bf16x8 (&gml)[RT / 2])
+{
+    constexpr int KS = RT / 2, HALF = RT / 2, SF = 2 * RT;
+    bf16x8 boh[KS], bol[KS], beh[KS], bel[KS];
+#pragma unroll
+    for (int q = 0; q < KS; ++q) {
+        split_bf16(Ro[2 * q], Ro[2 * q + 1], boh[q], bol[q]);
+        split_bf16(Re[2 * q], Re[2 * q + 1], beh[q], bel[q]);
+    }
+    // fragment f (odd hi, odd lo, even hi, even lo) of row tile I in K slab q:
+    // stage 2q + I / HALF, position I % HALF of that stage.  Slab u = I KS + q
+    // of the sequence is read D slabs ahead into ring buffer u % (D + 1).
+    constexpr int D = 2, NU = RT * KS;
+    bf16x8 x[D + 1][4];
+    auto load = [&](int u) {
+        const int I = u / KS, q = u % KS;
+#pragma unroll
+        for (int f = 0; f < 4; ++f)
+            x[u % (D + 1)][f] = __builtin_bit_cast(
+                bf16x8, xb[((2 * q + I / HALF) * SF + (I % HALF) * 4 + f) * 64 + lane]);
+    };
+#pragma unroll
+    for (int u = 0; u < D; ++u) load(u);
+    f32x4 aS[2], aA[2];
+#pragma unroll
+    for (int I = 0; I <= RT; ++I) {
+        if (I < RT) {
+            f32x4 s = f32x4{0.f, 0.f, 0.f, 0.f}, t = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int q = 0; q < KS; ++q) {
+                const int u = I * KS + q;
+                if (u + D < NU) load(u + D);
+                const bf16x8 *xf = x[u % (D + 1)];
+                s = mfma_bf16(xf[0], boh[q], s);
+                t = mfma_bf16(xf[2], beh[q], t);
+                s = mfma_bf16(xf[0], bol[q], s);
+                t = mfma_bf16(xf[2], bel[q], t);
+                s = mfma_bf16(xf[1], boh[q], s);
+                t = mfma_bf16(xf[3], beh[q], t);
+            }
+            aS[I & 1] = s;
+            aA[I & 1] = t;
+        }
+        if (I >= 1) {
+            const int P = I - 1;
+            bond_forces(aS[P & 1], aA[P & 1], alpha, lin, Gp[P], Gm[P]);
+            if (P & 1) {
+                split_bf16(Gp[P - 1], Gp[P], gph[P / 2], gpl[P / 2]);
+                split_bf16(Gm[P - 1], Gm[P], gmh[P / 2], gml[P / 2]);
+            }
+        }
+        // one scheduling region per row tile: the compiler interleaves the
+        // products, the reads and the forces inside it (measured faster than
+        // a prescribed interleave by group barriers)
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
 
 template <int RT, bool BF16, bool RESIDENT>
 __device__ __forceinline__ void fused_tiles(const BucketArgs &a, const LaunchArgs &la, int tile0,
@@ -370,7 +443,10 @@ __device__ __forceinline__ void fused_tiles(const BucketArgs &a, const LaunchArg
         }
         f32x4 Gp[RT], Gm[RT];
         [[maybe_unused]] bf16x8 gph[KS], gpl[KS], gmh[KS], gml[KS];
-        if (la.nonlinear) {
+        if constexpr (RESIDENT && BF16) {
+            if (la.nonlinear)
+                chi_forces_resident<RT>(xb, lane, Ro, Re, alpha, a.lin, Gp, Gm, gph, gpl, gmh, gml);
+        } else if (la.nonlinear) {
             // ---- u = chi R: half-bond rows I, K over mode slabs q
             f32x4 aS[RT], aA[RT];
 #pragma unroll

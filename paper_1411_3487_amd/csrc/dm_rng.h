@@ -100,17 +100,18 @@ __host__ __device__ __forceinline__ void normals4_f64(const Block4 &b, double z[
 
 #if defined(__HIP_DEVICE_COMPILE__) || defined(__HIPCC__)
 // Four N(0,1) in FP32 from the same bits, with the hardware transcendentals:
-// uniforms (x/256 + 1/2) 2^-24 (24 significant bits, never 0 or 1),
+// uniforms (x + 1/2) 2^-32 as in FP64, from x rounded to 24 significant bits
+// (never 0; 1 where x rounds to 2^32, which gives the normal 0),
 // v_log_f32 (log2), v_sqrt_f32, and v_sin/v_cos_f32, which take their
 // argument in revolutions, so sin(2 pi u) = sin_rev(u).
 __device__ __forceinline__ void normals4_f32(const Block4 &b, float z[4])
 {
-    const float scale = 5.9604644775390625e-8f;  // 2^-24
-    const float m2ln2 = -1.3862943611198906f;    // -2 ln 2
-    const float u0 = ((float)(b.v[0] >> 8) + 0.5f) * scale;
-    const float u1 = ((float)(b.v[1] >> 8) + 0.5f) * scale;
-    const float u2 = ((float)(b.v[2] >> 8) + 0.5f) * scale;
-    const float u3 = ((float)(b.v[3] >> 8) + 0.5f) * scale;
+    const float m2ln2 = -1.3862943611198906f;          // -2 ln 2
+    const float s32 = 2.3283064365386962890625e-10f;  // 2^-32
+    const float u0 = __builtin_fmaf((float)b.v[0], s32, 0.5f * s32);
+    const float u1 = __builtin_fmaf((float)b.v[1], s32, 0.5f * s32);
+    const float u2 = __builtin_fmaf((float)b.v[2], s32, 0.5f * s32);
+    const float u3 = __builtin_fmaf((float)b.v[3], s32, 0.5f * s32);
     const float ra = __builtin_amdgcn_sqrtf(m2ln2 * __builtin_amdgcn_logf(u0));
     const float rb = __builtin_amdgcn_sqrtf(m2ln2 * __builtin_amdgcn_logf(u2));
     z[0] = ra * __builtin_amdgcn_cosf(u1);
