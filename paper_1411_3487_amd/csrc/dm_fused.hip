@@ -566,19 +566,21 @@ __device__ __forceinline__ void fused_tiles(const BucketArgs &a, const LaunchArg
             const int t = RT + J;
             const bool couple = la.nonlinear && J < a.jc;
             if (couple) prefetch(t, s);
+            // coefficients first, so their LDS reads are in flight during the
+            // noise, and the cross-lane read of normal 0 between the two blocks
+            const f32x4 Eo = cf[(kEo * RT + J) * 4 + g], Wo = cf[(kWo * RT + J) * 4 + g];
+            const f32x4 Ee = cf[(kEe * RT + J) * 4 + g], We = cf[(kWe * RT + J) * 4 + g];
             const uint32_t ch =
                 after(chain, J ? Ro[J - 1][3] : (la.nonlinear ? Gm[0][0] : Re[0][0]));
             float z[8];
             normals4_f32(noise_bits(la.seed, (uint32_t)(8 * J + 2 * g), ch, k, (uint32_t)alpha,
                                     kTagMode),
                          z);
+            const float zn = __shfl(z[0], (lane + 16) & 63, 64);
             normals4_f32(noise_bits(la.seed, (uint32_t)(8 * J + 2 * g + 1), ch, k,
                                     (uint32_t)alpha, kTagMode),
                          z + 4);
-            const float zn = __shfl(z[0], (lane + 16) & 63, 64);
             if (J > 0) Re[J - 1][3] = __builtin_fmaf(g == 3 ? wcarry : 0.0f, zn, Re[J - 1][3]);
-            const f32x4 Eo = cf[(kEo * RT + J) * 4 + g], Wo = cf[(kWo * RT + J) * 4 + g];
-            const f32x4 Ee = cf[(kEe * RT + J) * 4 + g], We = cf[(kWe * RT + J) * 4 + g];
             f32x4 ao, ae;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
@@ -928,18 +930,20 @@ __device__ __forceinline__ void split_tile(const BucketArgs &a, const LaunchArgs
 #pragma unroll
                 for (int q = 0; q < DC; ++q) load_c(q);
             }
+            // coefficients first and the cross-lane read between the two
+            // blocks, as in the one-wavefront tiles
+            const f32x4 Eo = cf[(kEo * RT + J) * 4 + g], Wo = cf[(kWo * RT + J) * 4 + g];
+            const f32x4 Ee = cf[(kEe * RT + J) * 4 + g], We = cf[(kWe * RT + J) * 4 + g];
             const uint32_t ch = after(chain, ii ? Ro[ii - 1][3] : (la.nonlinear ? gdep : Re[0][0]));
             float z[8];
             normals4_f32(noise_bits(la.seed, (uint32_t)(8 * J + 2 * g), ch, k, (uint32_t)alpha,
                                     kTagMode),
                          z);
+            const float zn = __shfl(z[0], (lane + 16) & 63, 64);
+            if (lane < 16) cz[J * 16 + lane] = z[0];
             normals4_f32(noise_bits(la.seed, (uint32_t)(8 * J + 2 * g + 1), ch, k,
                                     (uint32_t)alpha, kTagMode),
                          z + 4);
-            const float zn = __shfl(z[0], (lane + 16) & 63, 64);
-            if (lane < 16) cz[J * 16 + lane] = z[0];
-            const f32x4 Eo = cf[(kEo * RT + J) * 4 + g], Wo = cf[(kWo * RT + J) * 4 + g];
-            const f32x4 Ee = cf[(kEe * RT + J) * 4 + g], We = cf[(kWe * RT + J) * 4 + g];
             f32x4 ao, ae;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
