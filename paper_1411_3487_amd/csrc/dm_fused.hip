@@ -156,15 +156,45 @@ __device__ __forceinline__ void bond_forces(const f32x4 aS, const f32x4 aA, int 
     // each component lane adds a third of the offset to its square, so the
     // sum over the chain's three lanes carries it once
     constexpr float kTiny3 = 1e-30f / 3.0f;
+    // level by level over the 8 independent sums, so that every lane move
+    // reads a value written several instructions earlier (a DPP read right
+    // after the write of its source costs wait states)
+    float up[4], um[4], vp[4], vm[4], sp[4], sm[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        const float up = aS[r] + aA[r], um = aS[r] - aA[r];
-        const float sp = comp_sum(__builtin_fmaf(up, up, kTiny3), alpha);
-        const float sm = comp_sum(__builtin_fmaf(um, um, kTiny3), alpha);
-        const float tp = __builtin_amdgcn_rsqf(sp) - lin;
-        const float gm = um * (__builtin_amdgcn_rsqf(sm) - lin);
-        Gp[r] = __builtin_fmaf(up, tp, gm);
-        Gm[r] = __builtin_fmaf(up, tp, -gm);
+        up[r] = aS[r] + aA[r];
+        um[r] = aS[r] - aA[r];
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        vp[r] = __builtin_fmaf(up[r], up[r], kTiny3);
+        vm[r] = __builtin_fmaf(um[r], um[r], kTiny3);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        sp[r] = vp[r] + dpp<kRowShl1>(vp[r]);
+        sm[r] = vm[r] + dpp<kRowShl1>(vm[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        sp[r] = sp[r] + dpp<kRowShl2>(vp[r]);  // complete at alpha == 0
+        sm[r] = sm[r] + dpp<kRowShl2>(vm[r]);
+    }
+    float p1[4], p2[4], m1[4], m2[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        p1[r] = dpp<kRowShr1>(sp[r]);
+        m1[r] = dpp<kRowShr1>(sm[r]);
+        p2[r] = dpp<kRowShr2>(sp[r]);
+        m2[r] = dpp<kRowShr2>(sm[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const float tp = __builtin_amdgcn_rsqf(alpha == 0 ? sp[r] : (alpha == 1 ? p1[r] : p2[r])) - lin;
+        const float gm =
+            um[r] * (__builtin_amdgcn_rsqf(alpha == 0 ? sm[r] : (alpha == 1 ? m1[r] : m2[r])) - lin);
+        Gp[r] = __builtin_fmaf(up[r], tp, gm);
+        Gm[r] = __builtin_fmaf(up[r], tp, -gm);
     }
 }
 
