@@ -180,19 +180,28 @@ __device__ __forceinline__ void bond_forces(const f32x4 aS, const f32x4 aA, int 
         sp[r] = sp[r] + dpp<kRowShl2>(vp[r]);  // complete at alpha == 0
         sm[r] = sm[r] + dpp<kRowShl2>(vm[r]);
     }
-    float p1[4], p2[4], m1[4], m2[4];
+    // kept at the x lanes only, then spread to the two lanes after each (the
+    // two lanes before an x lane hold zero, so the sums are exact)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        p1[r] = dpp<kRowShr1>(sp[r]);
-        m1[r] = dpp<kRowShr1>(sm[r]);
-        p2[r] = dpp<kRowShr2>(sp[r]);
-        m2[r] = dpp<kRowShr2>(sm[r]);
+        sp[r] = alpha == 0 ? sp[r] : 0.0f;
+        sm[r] = alpha == 0 ? sm[r] : 0.0f;
+    }
+    float bp[4], bm[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        bp[r] = sp[r] + dpp<kRowShr1>(sp[r]);
+        bm[r] = sm[r] + dpp<kRowShr1>(sm[r]);
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        const float tp = __builtin_amdgcn_rsqf(alpha == 0 ? sp[r] : (alpha == 1 ? p1[r] : p2[r])) - lin;
-        const float gm =
-            um[r] * (__builtin_amdgcn_rsqf(alpha == 0 ? sm[r] : (alpha == 1 ? m1[r] : m2[r])) - lin);
+        bp[r] = bp[r] + dpp<kRowShr2>(sp[r]);
+        bm[r] = bm[r] + dpp<kRowShr2>(sm[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const float tp = __builtin_amdgcn_rsqf(bp[r]) - lin;
+        const float gm = um[r] * (__builtin_amdgcn_rsqf(bm[r]) - lin);
         Gp[r] = __builtin_fmaf(up[r], tp, gm);
         Gm[r] = __builtin_fmaf(up[r], tp, -gm);
     }
