@@ -1173,15 +1173,19 @@ struct ObsArgs {
     int K, M, n, ntiles, accumulate;
 };
 
-// Observables of one tile (pos: [16][M] floats of LDS).
+// Observables of one tile.  LDS: pos [16][M] floats (positions about the
+// centre of mass, column = 3 chain + component), then msq [5][M] floats
+// (|R_p|^2 of each chain).
 template <int RT>
 __device__ __forceinline__ void obs_tile(const ObsArgs &a, int tile, float *pos)
 {
     const int M = a.M, H = M / 2;
+    float *msq = pos + 16 * M;
     const int lane = threadIdx.x & 63, col = lane & 15, g = lane >> 4;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int cl = col / 3, alpha = col - 3 * cl;
     const int nvalid = min(kChainsPerTile, a.n - kChainsPerTile * tile);
+    const size_t c0 = (size_t)kChainsPerTile * tile;
     f32x4 Ro[RT], Re[RT];
     const f32x4 *Rt = reinterpret_cast<const f32x4 *>(a.R) + (size_t)tile * 2 * RT * 64;
 #pragma unroll
@@ -1211,38 +1215,41 @@ __device__ __forceinline__ void obs_tile(const ObsArgs &a, int tile, float *pos)
             }
         }
     }
-    __syncthreads();
-    if (wave != 0) return;  // the rest is one wavefront's
-    // |R_p|^2 of p >= 1, summed over the chain's three component lanes
-    const int W = acc_width(M);
-    for (int t = 0; t < RT; ++t) {
+    // |R_p|^2 of p >= 1, summed over the chain's three component lanes: the
+    // mode tiles spread over the wavefronts, staged in LDS
+    for (int t = wave; t < RT; t += 4) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int j = 16 * t + 4 * g + r;
             const float vo = Ro[t][r];
             const float ve = j < H - 1 ? (float)((double)Re[t][r] / a.sig[j]) : 0.0f;
             const float so = comp_sum(vo * vo, alpha), se = comp_sum(ve * ve, alpha);
-            if (alpha == 0 && col < 15 && cl < nvalid) {
-                const size_t c = (size_t)kChainsPerTile * tile + cl;
+            if (alpha == 0 && col < 15) {
                 const int po = 2 * j + 1, pe = 2 * j + 2;
-                if (po < M) {
-                    a.m2[c * M + po] = so;
-                    if (a.accumulate) a.acc[c * W + DM_NACC_HEAD + po] += so;
-                }
-                if (pe < M) {
-                    a.m2[c * M + pe] = se;
-                    if (a.accumulate) a.acc[c * W + DM_NACC_HEAD + pe] += se;
-                }
+                if (po < M) msq[cl * M + po] = so;
+                if (pe < M) msq[cl * M + pe] = se;
             }
         }
     }
-    // 8 lanes per chain: bond lengths and the x extent
-    const int c8 = lane >> 3, part = lane & 7;
+    __syncthreads();
+    // written out chain by chain, consecutive modes in consecutive threads
+    const int W = acc_width(M);
+    for (int i = threadIdx.x; i < nvalid * M; i += blockDim.x) {
+        const int c = i / M, p = i - c * M;
+        if (p == 0) continue;  // the centre of mass, below
+        const float v = msq[c * M + p];
+        a.m2[(c0 + c) * M + p] = v;
+        if (a.accumulate) a.acc[(c0 + c) * W + DM_NACC_HEAD + p] += v;
+    }
+    // 32 lanes per chain (chains 0..4 in threads 0..159): bond lengths and the
+    // x extent
+    const int c8 = threadIdx.x >> 5, part = threadIdx.x & 31;
     const bool cv = c8 < nvalid;
+    if (c8 >= kChainsPerTile) return;
     const float *px = pos + 3 * (cv ? c8 : 0) * M, *py = px + M, *pz = py + M;
     double ls = 0.0, l2s = 0.0, xmin = 1e300, xmax = -1e300;
     if (cv) {
-        for (int nb = part; nb < M; nb += 8) {
+        for (int nb = part; nb < M; nb += 32) {
             const double x = px[nb];
             xmin = fmin(xmin, x);
             xmax = fmax(xmax, x);
@@ -1256,14 +1263,14 @@ __device__ __forceinline__ void obs_tile(const ObsArgs &a, int tile, float *pos)
         }
     }
 #pragma unroll
-    for (int off = 1; off < 8; off <<= 1) {
+    for (int off = 1; off < 32; off <<= 1) {
         ls += __shfl_xor(ls, off, 64);
         l2s += __shfl_xor(l2s, off, 64);
         xmin = fmin(xmin, __shfl_xor(xmin, off, 64));
         xmax = fmax(xmax, __shfl_xor(xmax, off, 64));
     }
     if (!cv || part != 0) return;
-    const size_t c = (size_t)kChainsPerTile * tile + c8;
+    const size_t c = c0 + c8;
     const double *r0 = a.R0 + (size_t)tile * 16 + 3 * c8;
     const double rs = 1.0 / sqrt((double)M);
     double o[DM_NCHAIN_OBS];
@@ -1969,7 +1976,7 @@ template <int RT>
 static void launch_obs(const ObsArgs &a, int nwg, hipStream_t st)
 {
     hipLaunchKernelGGL(fused_obs_kernel<RT>, dim3(nwg), dim3(256),
-                       sizeof(float) * 16 * (size_t)a.M, st, a);
+                       sizeof(float) * (16 + kChainsPerTile) * (size_t)a.M, st, a);
 }
 
 hipError_t fused_snapshot_alloc(FusedBucket &f)
