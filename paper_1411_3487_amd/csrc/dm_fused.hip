@@ -858,20 +858,100 @@ __device__ __forceinline__ void split_tile(const BucketArgs &a, const LaunchArgs
             for (int f = 0; f < 4; ++f)
                 dst[4 * ii + f] = frag((q * RT + wave + P * ii) * 4 + f);
     };
+    // Split BF16 runs u = chi R own row tile by own row tile (see the step
+    // loop); at RT = 16 its fragments stream through a ring of RL entries
+    // (own row tile ii, K slab q) in that order instead of the slab ring.
+    constexpr bool ROWS = BF16;
+    constexpr bool RING = ROWS && DU < KS;
+    constexpr int RL = 4;
+    [[maybe_unused]] f32x4 xr[RL][4];
+    auto load_r = [&](int u) {
+        const int ii = u / KS, q = u % KS;
+#pragma unroll
+        for (int f = 0; f < 4; ++f) xr[u % RL][f] = frag((q * RT + wave + P * ii) * 4 + f);
+    };
     if (la.nonlinear) {
 #pragma unroll
         for (int ii = 0; ii < NJ; ++ii) put_state(ii);
     }
     __syncthreads();  // coefficients and amplitudes in LDS
     if (la.nonlinear) {
+        if constexpr (RING) {
 #pragma unroll
-        for (int q = 0; q < DU; ++q) load_u(q, xu[q]);
+            for (int u = 0; u < RL; ++u) load_r(u);
+        } else {
+#pragma unroll
+            for (int q = 0; q < DU; ++q) load_u(q, xu[q]);
+        }
     }
 
     for (int s = 0; s < la.n_steps; ++s) {
         const int64_t k = step0 + s;
         float gdep = 0.0f;  // last force written: keeps the noise below the forces
-        if (la.nonlinear) {
+        if (ROWS && la.nonlinear) {
+            // ---- u = chi R own row tile by own row tile: the 24 products of
+            // row tile ii over the K slabs in order (each accumulator sees the
+            // products of the slab-by-slab form in the same order: same bits),
+            // the B operands read from LDS one slab ahead, and the bond forces
+            // of row tile ii - 1 (split and written to LDS) computed between
+            // the products, where the VALU work issues beside the matrix cores
+            constexpr int NU = NJ * KS;
+            f32x4 pS[2], pA[2];
+            f32x4 bn[4];
+            slab4(Rb, 0, bn, lane);
+#pragma unroll
+            for (int ii = 0; ii <= NJ; ++ii) {
+                if (ii < NJ) {
+                    f32x4 sacc = f32x4{0.f, 0.f, 0.f, 0.f}, tacc = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int q = 0; q < KS; ++q) {
+                        const int u = ii * KS + q;
+                        f32x4 bc[4];
+#pragma unroll
+                        for (int k2 = 0; k2 < 4; ++k2) bc[k2] = bn[k2];
+                        if (u + 1 < NU) slab4(Rb, (q + 1) % KS, bn, lane);
+                        f32x4 xf[4];
+#pragma unroll
+                        for (int f = 0; f < 4; ++f) {
+                            if constexpr (RING)
+                                xf[f] = xr[u % RL][f];
+                            else
+                                xf[f] = xu[q][4 * ii + f];
+                        }
+                        if constexpr (RING) {
+                            if (u + RL < NU) load_r(u + RL);
+                        }
+                        const bf16x8 boh = __builtin_bit_cast(bf16x8, bc[0]);
+                        const bf16x8 bol = __builtin_bit_cast(bf16x8, bc[1]);
+                        const bf16x8 beh = __builtin_bit_cast(bf16x8, bc[2]);
+                        const bf16x8 bel = __builtin_bit_cast(bf16x8, bc[3]);
+                        sacc = mfma_bf16(__builtin_bit_cast(bf16x8, xf[0]), boh, sacc);
+                        tacc = mfma_bf16(__builtin_bit_cast(bf16x8, xf[2]), beh, tacc);
+                        sacc = mfma_bf16(__builtin_bit_cast(bf16x8, xf[0]), bol, sacc);
+                        tacc = mfma_bf16(__builtin_bit_cast(bf16x8, xf[2]), bel, tacc);
+                        sacc = mfma_bf16(__builtin_bit_cast(bf16x8, xf[1]), boh, sacc);
+                        tacc = mfma_bf16(__builtin_bit_cast(bf16x8, xf[3]), beh, tacc);
+                    }
+                    pS[ii & 1] = sacc;
+                    pA[ii & 1] = tacc;
+                }
+                if (ii >= 1) {
+                    const int pi = ii - 1, I = wave + P * pi;
+                    f32x4 Gp, Gm;
+                    bond_forces(pS[pi & 1], pA[pi & 1], alpha, a.lin, Gp, Gm);
+                    bf16x4 h, l;
+                    split_half(Gp, h, l);
+                    put_half(Gb, I, 0, lane, h);
+                    put_half(Gb, I, 1, lane, l);
+                    split_half(Gm, h, l);
+                    put_half(Gb, I, 2, lane, h);
+                    put_half(Gb, I, 3, lane, l);
+                    gdep = Gm[0];
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            lds_barrier();  // B
+        } else if (la.nonlinear) {
             // ---- u = chi R for the own half-bond row tiles
             f32x4 aS[NJ], aA[NJ];
 #pragma unroll
@@ -1067,8 +1147,13 @@ __device__ __forceinline__ void split_tile(const BucketArgs &a, const LaunchArgs
         }
         if constexpr (DU < KS) {
             if (la.nonlinear) {
+                if constexpr (RING) {
 #pragma unroll
-                for (int q = 0; q < DU; ++q) load_u(q, xu[q]);
+                    for (int u = 0; u < RL; ++u) load_r(u);
+                } else {
+#pragma unroll
+                    for (int q = 0; q < DU; ++q) load_u(q, xu[q]);
+                }
             }
         }
         lds_barrier();  // C
