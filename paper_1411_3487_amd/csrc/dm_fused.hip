@@ -931,6 +931,9 @@ __device__ __forceinline__ void split_tile(const BucketArgs &a, const LaunchArgs
                         tacc = mfma_bf16(__builtin_bit_cast(bf16x8, xf[2]), bel, tacc);
                         sacc = mfma_bf16(__builtin_bit_cast(bf16x8, xf[1]), boh, sacc);
                         tacc = mfma_bf16(__builtin_bit_cast(bf16x8, xf[3]), beh, tacc);
+                        // streamed fragments: each slab its own region, so the
+                        // ring's loads are not hoisted ahead of their slot
+                        if constexpr (RING) __builtin_amdgcn_sched_barrier(0);
                     }
                     pS[ii & 1] = sacc;
                     pA[ii & 1] = tacc;
