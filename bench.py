@@ -928,6 +928,10 @@ def main():
     ctx.set_params([M], [args.dtau], T_star=T_STAR_DSDNA, nu=NU_DSDNA, sample_every=0,
                    tiles_per_wg=int(tiling["tpw"]), table_mode=shape)
     k_launch = se if se > 0 else 100
+    # launch durations settle over the first ~20 launches after the
+    # autotuner (about 830 -> 750 us at 4096 x 256): 20 untimed launches back
+    # to back, then the median of 9 timed ones
+    ctx.step_modes(20 * k_launch)
     kern = sorted(time_steps(ctx, torch, k_launch, stream) for _ in range(9))[4]
     ctx.close()
 
