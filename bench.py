@@ -60,7 +60,7 @@ def parse():
                     "replayed graphs of the sampling blocks")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--table-mode", default="auto",
-                    choices=["auto", "resident", "streamed", "split"],
+                    choices=["auto", "resident", "streamed", "split", "split8"],
                     help="force a tile shape of the fused launch where it exists (modes and "
                          "uneven workloads; overrides the autotuner)")
     ap.add_argument("--fp64-steps", type=int, default=0,
@@ -444,14 +444,16 @@ def coarse_workload(args):
 
 
 def profile_launches(args):
-    """N launches of 200 mode steps of the default workload, no sampling."""
+    """N launches of 200 mode steps of the default workload, no sampling, on
+    the untimed default tile shape or the one --table-mode forces."""
     import torch
     from paper_1411_3487_amd import Context, inputs, NU_DSDNA, T_STAR_DSDNA
     torch.cuda.set_device(0)
     b = 1.0 / (1.0 - 2.0 * NU_DSDNA)
     pos = inputs.straight_chains(args.chains, args.beads, b, seed=1, random_orientation=True)
     ctx = Context(pos, seed=1, precision=args.precision, stream=torch.cuda.current_stream())
-    ctx.set_params([args.beads], [args.dtau], T_star=T_STAR_DSDNA, nu=NU_DSDNA)
+    ctx.set_params([args.beads], [args.dtau], T_star=T_STAR_DSDNA, nu=NU_DSDNA,
+                   table_mode=args.table_mode)
     for _ in range(args.profile_launches):
         ctx.step_modes(200)
     torch.cuda.synchronize()
@@ -910,7 +912,8 @@ def main():
                    sample_every=se, use_graphs=not args.no_graphs,
                    autotune=not args.no_autotune, table_mode=args.table_mode)
     tiling, report = ctx.tiling()[0], ctx.tuning_report()
-    shape = "split" if tiling["split"] else ("resident" if tiling["resident"] else "streamed")
+    shape = {0: "resident" if tiling["resident"] else "streamed", 1: "split",
+             2: "split8"}[int(tiling["split"])]
     ctx.step_modes(warmup)
     torch.cuda.synchronize()
     n0 = ctx.accumulators()[0]["n_samples"]
@@ -986,7 +989,8 @@ def main():
         "state_finite": finite,
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
-                     "kernel": f"fused_kernel ({args.precision}), {k_launch} steps per launch",
+                     "kernel": f"{'split_wide_kernel' if shape == 'split8' else 'fused_kernel'} "
+                               f"({args.precision}), {k_launch} steps per launch",
                      "kernel_ms": kern * 1e3, "flops_per_chain_step": exec_flops},
     }
     # Table 2 context: simulated time per hour of computing for one chain

@@ -134,7 +134,8 @@ extern "C" {
 #define DM_TI_ITEMS      6  /* workgroups of this bucket per launch */
 #define DM_TI_ITEM_US    7  /* measured us per workgroup-step (autotune), or 0 */
 #define DM_TI_SPLIT      8  /* 1: one tile per workgroup, its bond rows and
-                               mode tiles divided among 4 wavefronts */
+                               mode tiles divided among 4 wavefronts; 2: among
+                               8 (two per SIMD; split-BF16, RT = 8 and 16) */
 
 typedef struct dm_ctx dm_ctx;
 
@@ -182,9 +183,10 @@ typedef struct {
                                 divided among 4 wavefronts: for launches
                                 with fewer tiles than SIMDs; lengths with
                                 RT = 4, 8, 12, 16, i.e. 65..128, 193..256,
-                                321..384, 449..512 beads), each where that
-                                form exists for the length (it overrides the
-                                autotuner).  Automatic without autotune:
+                                321..384, 449..512 beads), 4 = split tiles
+                                over 8 wavefronts (split-BF16, RT = 8 and
+                                16), each where that form exists for the
+                                length (it overrides the autotuner).  Automatic without autotune:
                                 split tiles where they exist when the launch
                                 has no more tiles than compute units, else
                                 resident tables where they fit.  Results do

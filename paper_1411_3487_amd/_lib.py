@@ -220,8 +220,8 @@ class Context:
         p.use_graphs = 1 if use_graphs else 0
         p.tiles_per_wg = tiles_per_wg
         p.corr_lags = corr_lags
-        p.table_mode = {"auto": 0, "resident": 1, "streamed": 2, "split": 3}.get(table_mode,
-                                                                                 table_mode)
+        p.table_mode = {"auto": 0, "resident": 1, "streamed": 2, "split": 3,
+                        "split8": 4}.get(table_mode, table_mode)
         self._check(self.lib.dm_set_params(self.h, ctypes.byref(p)))
 
     def tiling(self) -> list:

@@ -614,8 +614,8 @@ int dm_set_params(dm_ctx *ctx, const dm_params *p)
     if (p->n_lengths <= 0 || !p->lengths || !p->dt)
         return fail(ctx, DM_EINVAL, "lengths / dt tables are empty");
     if (p->sample_every < 0) return fail(ctx, DM_EINVAL, "sample_every must be >= 0");
-    if (p->tiles_per_wg < 0 || p->tiles_per_wg > 4 || p->table_mode < 0 || p->table_mode > 3)
-        return fail(ctx, DM_EINVAL, "tiles_per_wg must be 0..4 and table_mode 0..3");
+    if (p->tiles_per_wg < 0 || p->tiles_per_wg > 4 || p->table_mode < 0 || p->table_mode > 4)
+        return fail(ctx, DM_EINVAL, "tiles_per_wg must be 0..4 and table_mode 0..4");
     if (p->corr_lags < 0 || p->corr_lags > 14)
         return fail(ctx, DM_EINVAL, "corr_lags must be 0..14");
     std::vector<double> dtau(ctx->buckets.size());

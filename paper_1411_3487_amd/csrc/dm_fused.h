@@ -27,7 +27,8 @@ struct FusedBucket {
     int resident = 0;        // tables held in LDS for the whole launch
     int tpw = 4;             // tiles per workgroup (1..4; 4 when streamed, 1 split)
     int split = 0;           // 1: one tile per workgroup, its rows and modes
-                             // divided among the 4 wavefronts
+                             // divided among 4 wavefronts; 2: among 8
+                             // (split-BF16, RT = 8 and 16, a kernel of its own)
     double item_us = 0.0;    // measured time of one workgroup-step (0: model)
     int n = 0;               // chains
     const int32_t *ids = nullptr;  // device: global chain index per local chain
@@ -48,6 +49,7 @@ hipError_t fused_set_coefs(FusedBucket &f, const ModeCoefs &mc, int M, double li
 // One launch over all buckets: a list of workgroup items, longest first.
 struct FusedPlan {
     int bf16 = 0, nitems = 0, nbuckets = 0;
+    int nwide = 0;  // the last nwide items run on 8-wavefront split tiles
     void *d_buckets = nullptr, *d_items = nullptr;
 };
 // Build the launch for the buckets (all of one precision) with their current
@@ -69,8 +71,8 @@ hipError_t fused_autotune(std::vector<FusedBucket *> &bs, uint64_t seed, int ste
 // measured by the autotuner, else the cost model.
 double fused_item_us(const FusedBucket &f);
 // Force a tile shape where it exists: table_mode 1 resident, 2 streamed,
-// 3 split (0 keeps the current); tpw 1..4 where resident (0 keeps the
-// current).
+// 3 split over 4 wavefronts, 4 split over 8 (0 keeps the current); tpw 1..4
+// where resident (0 keeps the current).
 void fused_force_shape(FusedBucket &f, int table_mode, int tpw);
 // Device step counter of replayed graphs: *d_step = value, *d_step += n.
 hipError_t fused_set_step(int64_t *d_step, int64_t value, hipStream_t st);

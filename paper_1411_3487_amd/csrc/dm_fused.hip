@@ -716,12 +716,15 @@ __device__ __forceinline__ void fused_tiles(const BucketArgs &a, const LaunchArg
 }
 
 // ---- Split tile: one tile of 5 chains per workgroup, its work divided
-// among the 4 wavefronts, for launches with fewer tiles than the GPU has
-// SIMDs (with one wavefront per tile, 1024 chains make 205 wavefronts).
-// Wavefront w owns the mode tiles J = w, w + 4, ... (their amplitudes, noise
-// and update) and the half-bond row tiles I = w, w + 4, ... (their rows of
+// among P = 4 (or 8) wavefronts, for launches with fewer tiles than the GPU
+// has SIMDs (with one wavefront per tile, 1024 chains make 205 wavefronts).
+// Wavefront w owns the mode tiles J = w, w + P, ... (their amplitudes, noise
+// and update) and the half-bond row tiles I = w, w + P, ... (their rows of
 // u = chi R and their bond forces); the round-robin spreads the few coupled
-// mode tiles J < jc over the wavefronts.  Each step they exchange through LDS
+// mode tiles J < jc over the wavefronts.  With 8 wavefronts (split-BF16, RT
+// = 8 and 16, a kernel of its own with at most 256 registers per lane) each
+// SIMD runs two of the tile's wavefronts, whose waits and matrix products
+// overlap the other's vector work.  Each step they exchange through LDS
 // what their products take from the others:
 //   Rb  the amplitudes (split BF16 or FP32), the B operand of u = chi R;
 //   Gb  the bond forces G+ and G- (split or FP32), the B operand of the
@@ -780,11 +783,10 @@ __device__ __forceinline__ void slab4(const f32x4 *buf, int q, f32x4 *dst, int l
     for (int k = 0; k < 4; ++k) dst[k] = buf[(4 * q + k) * 64 + lane];
 }
 
-template <int RT, bool BF16>
+template <int RT, bool BF16, int P = 4>  // P: wavefronts of the workgroup
 __device__ __forceinline__ void split_tile(const BucketArgs &a, const LaunchArgs &la, int tile,
                                            int64_t step0, f32x4 *cf, f32x4 *xb)
 {
-    constexpr int P = 4;          // wavefronts
     constexpr int NJ = RT / P;    // mode tiles and row tiles of each
     constexpr int KS = RT / 2;    // K slabs
     constexpr int SF = 2 * RT;    // fragments per table stage
@@ -1217,12 +1219,36 @@ __global__ __launch_bounds__(256) void fused_kernel(LaunchArgs la)
     }
 }
 
+// Split tiles of 8 wavefronts (split-BF16): two wavefronts of the tile per
+// SIMD, so at most 256 registers per lane; the exchange buffers of the
+// largest tile (RT = 16) in LDS.
+constexpr int kWideLds = kKinds * 16 * 4 + 4 * 16 * 64 + 4 * 16;  // f32x4
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void split_wide_kernel(LaunchArgs la)
+{
+    __shared__ f32x4 lds[kWideLds];
+    const Item it = la.items[blockIdx.x];
+    const BucketArgs a = la.buckets[it.bucket];
+    const int64_t step0 = la.step ? *la.step : la.step0;
+    switch (a.variant) {
+    case 13: split_tile<8, true, 8>(a, la, it.tile0, step0, lds, lds + kKinds * 8 * 4); break;
+    case 14: split_tile<16, true, 8>(a, la, it.tile0, step0, lds, lds + kKinds * 16 * 4); break;
+    default: break;
+    }
+}
+
 // Kernel variant of a tile shape: resident tables exist for RT <= 8,
-// streamed ones for RT >= 8, split tiles for RT = 4, 8, 12, 16.
+// streamed ones for RT >= 8, split tiles for RT = 4, 8, 12, 16, and split
+// tiles of 8 wavefronts for RT = 8, 16 in split-BF16.
 int variant_of(int RT, bool resident) { return resident ? RT / 2 - 1 : 4 + (RT - 8) / 2; }
 bool has_variant(int RT, bool resident) { return resident ? RT <= 8 : RT >= 8; }
-int split_variant(int RT) { return 8 + RT / 4; }
-bool has_split(int RT) { return RT >= 4 && RT <= 16 && RT % 4 == 0; }
+int split_variant(int RT, int waves) { return waves == 8 ? 12 + RT / 8 : 8 + RT / 4; }
+bool has_split(int RT, int waves, bool bf16)
+{
+    return waves == 8 ? bf16 && (RT == 8 || RT == 16) : RT >= 4 && RT <= 16 && RT % 4 == 0;
+}
+// Wavefronts of a bucket's split tiles (split = 1: 4, split = 2: 8).
+static int split_waves(const FusedBucket &f) { return f.split == 2 ? 8 : 4; }
 
 // Slot of mode p >= 1 of (local chain j, component alpha) in the state:
 // odd p at half-mode slot (p - 1)/2, even p at p/2 - 1.
@@ -1735,7 +1761,7 @@ static BucketArgs bucket_args(const FusedBucket &f)
     a.ntiles = f.ntiles;
     a.x_bytes = (int)x_bytes(f.RT);
     a.jc = f.JC;
-    a.variant = f.split ? split_variant(f.RT) : variant_of(f.RT, f.resident != 0);
+    a.variant = f.split ? split_variant(f.RT, split_waves(f)) : variant_of(f.RT, f.resident != 0);
     a.tpw = f.tpw;
     a.lin = f.lin;
     a.W0 = f.W0;
@@ -1745,12 +1771,13 @@ static BucketArgs bucket_args(const FusedBucket &f)
 
 // Cost model of one workgroup-step when nothing was measured: the MFMA and
 // table work grow as RT^2, the noise and forces as RT; a split tile takes
-// about a third of a wavefront's time for one tile.
+// about a third of a wavefront's time for one tile (a quarter on 8
+// wavefronts).
 static double model_us(const FusedBucket &f)
 {
     const double rt = f.RT;
     const double us = 0.12 * rt * rt + 0.3 * rt + (f.resident ? 0.0 : 0.02 * rt * rt);
-    return f.split ? us / 3.0 : us;
+    return f.split == 2 ? us / 4.0 : f.split ? us / 3.0 : us;
 }
 
 double fused_item_us(const FusedBucket &f) { return f.item_us > 0.0 ? f.item_us : model_us(f); }
@@ -1786,16 +1813,14 @@ void fused_plan_free(FusedPlan &p)
     p = FusedPlan();
 }
 
-// The bodies of all tile shapes are inlined into the one launch kernel, whose
+// The bodies of all tile shapes are inlined into the launch kernels, whose
 // private (spill) segment must stay within the HIP runtime's default
 // per-thread stack of 1 KB: a larger segment is refused here rather than
 // launched.
 constexpr size_t kMaxPrivateBytes = 1024;
-static hipError_t check_private_segment(bool bf16)
+static hipError_t check_private_segment(const void *fn)
 {
     hipFuncAttributes at;
-    const void *fn = bf16 ? reinterpret_cast<const void *>(&fused_kernel<true>)
-                          : reinterpret_cast<const void *>(&fused_kernel<false>);
     hipError_t e = hipFuncGetAttributes(&at, fn);
     if (e != hipSuccess) return e;
     return at.localSizeBytes <= kMaxPrivateBytes ? hipSuccess : hipErrorInvalidConfiguration;
@@ -1807,20 +1832,33 @@ hipError_t fused_plan(FusedPlan &p, const std::vector<const FusedBucket *> &bs, 
     fused_plan_free(p);
     if (bs.empty()) return hipSuccess;
     p.bf16 = bs[0]->bf16;
-    hipError_t e = check_private_segment(p.bf16 != 0);
+    hipError_t e = check_private_segment(p.bf16 ? reinterpret_cast<const void *>(&fused_kernel<true>)
+                                                : reinterpret_cast<const void *>(&fused_kernel<false>));
     if (e != hipSuccess) return e;
     std::vector<BucketArgs> ba;
+    bool wide = false;
     for (const FusedBucket *f : bs) {
         if (f->bf16 != p.bf16) return hipErrorInvalidValue;
-        const bool ok = f->split ? has_split(f->RT) && f->tpw == 1 && !f->resident
+        const bool ok = f->split ? f->split <= 2 && has_split(f->RT, split_waves(*f), f->bf16 != 0) &&
+                                       f->tpw == 1 && !f->resident
                                  : has_variant(f->RT, f->resident != 0) && f->tpw >= 1 &&
                                        f->tpw <= 4 && (f->resident || f->tpw == 4);
         if (!ok) return hipErrorInvalidValue;
+        wide = wide || f->split == 2;
         ba.push_back(bucket_args(*f));
     }
+    if (wide && (e = check_private_segment(reinterpret_cast<const void *>(&split_wide_kernel))) !=
+                    hipSuccess)
+        return e;
     std::vector<Item> items = ordered_items(bs);
     if (max_items > 0 && (int)items.size() > max_items) items.resize(max_items);
+    // the items of 8-wavefront split tiles go to their own kernel, after the
+    // others (each part keeps its longest-first order)
+    std::stable_partition(items.begin(), items.end(),
+                          [&](const Item &it) { return bs[it.bucket]->split != 2; });
     p.nitems = (int)items.size();
+    p.nwide = (int)std::count_if(items.begin(), items.end(),
+                                 [&](const Item &it) { return bs[it.bucket]->split == 2; });
     p.nbuckets = (int)bs.size();
     if ((e = hipMalloc(&p.d_buckets, sizeof(BucketArgs) * ba.size())) != hipSuccess) return e;
     if ((e = hipMalloc(&p.d_items, sizeof(Item) * std::max<size_t>(1, items.size()))) !=
@@ -1847,10 +1885,19 @@ hipError_t fused_launch(const FusedPlan &p, uint64_t seed, int64_t step0, const 
     la.seed = seed;
     la.n_steps = n_steps;
     la.nonlinear = nonlinear;
-    if (p.bf16)
-        hipLaunchKernelGGL(fused_kernel<true>, dim3(p.nitems), dim3(256), 0, st, la);
-    else
-        hipLaunchKernelGGL(fused_kernel<false>, dim3(p.nitems), dim3(256), 0, st, la);
+    const int nmain = p.nitems - p.nwide;
+    if (nmain > 0) {
+        if (p.bf16)
+            hipLaunchKernelGGL(fused_kernel<true>, dim3(nmain), dim3(256), 0, st, la);
+        else
+            hipLaunchKernelGGL(fused_kernel<false>, dim3(nmain), dim3(256), 0, st, la);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (p.nwide > 0) {
+        la.items += nmain;
+        hipLaunchKernelGGL(split_wide_kernel, dim3(p.nwide), dim3(512), 0, st, la);
+    }
     return hipGetLastError();
 }
 
@@ -1910,7 +1957,8 @@ hipError_t fused_autotune(std::vector<FusedBucket *> &bs, uint64_t seed, int ste
                 list.push_back({res, tpw, 0, 0.0});
             }
         }
-        if (has_split(f.RT)) list.push_back({0, 1, 1, 0.0});
+        if (has_split(f.RT, 4, f.bf16 != 0)) list.push_back({0, 1, 1, 0.0});
+        if (has_split(f.RT, 8, f.bf16 != 0)) list.push_back({0, 1, 2, 0.0});
         for (Cand &c : list) {
             if (e != hipSuccess) break;
             t.resident = c.resident;
@@ -1945,15 +1993,19 @@ hipError_t fused_autotune(std::vector<FusedBucket *> &bs, uint64_t seed, int ste
     size_t combos = 1;
     for (auto &l : cands) combos = std::min<size_t>(combos * std::max<size_t>(1, l.size()), 1 << 20);
     std::vector<int> pick(bs.size(), 0), cur(bs.size(), 0);
+    // the 8-wavefront split tiles run in a kernel of their own after the
+    // others: the two makespans add
     auto evaluate = [&](const std::vector<int> &sel) {
-        std::vector<double> cost;
+        std::vector<double> cost, wcost;
         for (size_t b = 0; b < bs.size(); ++b) {
             const Cand &c = cands[b][sel[b]];
             const int ni = (bs[b]->ntiles + c.tpw - 1) / c.tpw;
-            cost.insert(cost.end(), (size_t)ni, c.us);
+            std::vector<double> &v = c.split == 2 ? wcost : cost;
+            v.insert(v.end(), (size_t)ni, c.us);
         }
         std::sort(cost.begin(), cost.end(), std::greater<double>());
-        return makespan(cost, ncu);
+        std::sort(wcost.begin(), wcost.end(), std::greater<double>());
+        return makespan(cost, ncu) + makespan(wcost, ncu);
     };
     if (combos <= 4096) {
         double best = 1e300;
@@ -2011,8 +2063,12 @@ hipError_t fused_autotune(std::vector<FusedBucket *> &bs, uint64_t seed, int ste
         f.item_us = c.us;
         for (size_t k = 0; k < cands[b].size(); ++k) {
             const Cand &ck = cands[b][k];
-            snprintf(line, sizeof line, "RT=%d %s tpw=%d: %.2f us/step%s\n", f.RT,
-                     ck.split ? "split" : (ck.resident ? "resident" : "streamed"), ck.tpw, ck.us,
+            const char *shape = ck.split == 2 ? "split8"
+                                : ck.split    ? "split"
+                                : ck.resident ? "resident"
+                                              : "streamed";
+            snprintf(line, sizeof line, "RT=%d %s tpw=%d: %.2f us/step%s\n", f.RT, shape, ck.tpw,
+                     ck.us,
                      (int)k == pick[b] ? "  <- chosen" : "");
             report += line;
         }
@@ -2031,9 +2087,10 @@ void fused_force_shape(FusedBucket &f, int table_mode, int tpw)
         f.split = 0;
         f.tpw = 4;
         f.item_us = 0.0;
-    } else if (table_mode == 3 && has_split(f.RT)) {
+    } else if ((table_mode == 3 || table_mode == 4) &&
+               has_split(f.RT, table_mode == 4 ? 8 : 4, f.bf16 != 0)) {
         f.resident = 0;
-        f.split = 1;
+        f.split = table_mode == 4 ? 2 : 1;
         f.tpw = 1;
         f.item_us = 0.0;
     }
