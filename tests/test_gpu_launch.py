@@ -185,6 +185,32 @@ def test_split_tiles_of_8_wavefronts_bit_identical(kw):
     assert same(runs["split8"][0], runs["streamed"][0])
 
 
+def test_split_tiles_of_8_wavefronts_mixed_plan_under_graphs():
+    """A plan of both kernels (8-wavefront split tiles for 256 and 512
+    beads, one-wavefront tiles for the other lengths) replayed as sampling
+    blocks with deferred observables equals the eager default shapes:
+    states, accumulators and correlators."""
+    beads = inputs.mixed_lengths(61, SPLIT_LENS, seed=5)
+    chains = inputs.mixed_chains(beads, B_FAC, seed=5)
+    res = []
+    for mode, graphs in (("split8", True), ("auto", False)):
+        with Context(chains, seed=7, precision="bf16x3") as c:
+            c.set_params(SPLIT_LENS, [SPLIT_DTAU[m] for m in SPLIT_LENS], T_star=TS, nu=NU,
+                         sample_every=10, use_graphs=graphs, table_mode=mode, corr_lags=3)
+            if mode == "split8":
+                assert sorted({int(t["split"]) for t in c.tiling()}) == [0, 2]
+            c.step_modes(45)
+            c.step_modes(30)
+            res.append((c.modes(), c.accumulators()))
+    assert same(res[0][0], res[1][0])
+    for a, b in zip(res[0][1], res[1][1]):
+        assert a["n_samples"] == b["n_samples"] == 7
+        for k in ("bond", "L2", "msd_cm"):
+            assert a[k] == b[k], k
+        assert np.array_equal(a["modes"], b["modes"])
+        assert np.array_equal(a["corr"], b["corr"])
+
+
 def test_split_tiles_of_8_wavefronts_graphs_and_fp32():
     """8-wavefront split tiles under replayed sampling blocks equal the eager
     one-wavefront tiles (states, accumulators, correlators); in FP32 the form
