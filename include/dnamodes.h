@@ -186,11 +186,14 @@ typedef struct {
                                 321..384, 449..512 beads), 4 = split tiles
                                 over 8 wavefronts (split-BF16, RT = 8 and
                                 16), each where that form exists for the
-                                length (it overrides the autotuner).  Automatic without autotune:
-                                split tiles where they exist when the launch
-                                has no more tiles than compute units, else
-                                resident tables where they fit.  Results do
-                                not depend on the tile shape */
+                                length (it overrides the autotuner).
+                                Automatic without autotune: split tiles
+                                where they exist when the launch has no
+                                more tiles than compute units (of 8
+                                wavefronts when every length has that
+                                form), else resident tables where they
+                                fit.  Results do not depend on the tile
+                                shape */
     int32_t corr_lags;       /* 0..14: number of lags of the time
                                 correlations in the accumulators (a ring of
                                 2^(corr_lags-1) past samples per chain is

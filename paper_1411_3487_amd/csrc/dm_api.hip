@@ -688,11 +688,19 @@ int dm_set_params(dm_ctx *ctx, const dm_params *p)
             DM_HIP(ctx, dm::fused_autotune(fb, ctx->seed, 64, ctx->stream, ctx->tune_report));
         } else if (!p->table_mode) {
             // untimed: split tiles when a wavefront per tile would leave
-            // compute units idle
+            // compute units idle; of 8 wavefronts when every bucket has that
+            // form (one launch of their kernel), else of 4
             size_t tiles = 0;
             for (const Bucket &b : ctx->buckets) tiles += (size_t)b.fused.ntiles;
-            if (ctx->ncu > 0 && tiles <= (size_t)ctx->ncu)
-                for (Bucket &b : ctx->buckets) dm::fused_force_shape(b.fused, 3, 0);
+            if (ctx->ncu > 0 && tiles <= (size_t)ctx->ncu) {
+                bool wide = true;
+                for (Bucket &b : ctx->buckets) {
+                    dm::fused_force_shape(b.fused, 4, 0);
+                    wide = wide && b.fused.split == 2;
+                }
+                if (!wide)
+                    for (Bucket &b : ctx->buckets) dm::fused_force_shape(b.fused, 3, 0);
+            }
         }
         if (p->tiles_per_wg || p->table_mode)
             for (Bucket &b : ctx->buckets)
