@@ -612,11 +612,11 @@ __device__ __forceinline__ void fused_tiles(const BucketArgs &a, const LaunchArg
             const uint32_t ch =
                 after(chain, J ? Ro[J - 1][3] : (la.nonlinear ? Gm[0][0] : Re[0][0]));
             float z[8];
-            normals4_f32(noise_bits(la.seed, (uint32_t)(8 * J + 2 * g), ch, k, (uint32_t)alpha,
+            scaled_normals4_f32(noise_bits(la.seed, (uint32_t)(8 * J + 2 * g), ch, k, (uint32_t)alpha,
                                     kTagMode),
                          z);
             const float zn = __shfl(z[0], (lane + 16) & 63, 64);
-            normals4_f32(noise_bits(la.seed, (uint32_t)(8 * J + 2 * g + 1), ch, k,
+            scaled_normals4_f32(noise_bits(la.seed, (uint32_t)(8 * J + 2 * g + 1), ch, k,
                                     (uint32_t)alpha, kTagMode),
                          z + 4);
             if (J > 0) Re[J - 1][3] = __builtin_fmaf(g == 3 ? wcarry : 0.0f, zn, Re[J - 1][3]);
@@ -1060,12 +1060,12 @@ __device__ __forceinline__ void split_tile(const BucketArgs &a, const LaunchArgs
             const f32x4 Ee = cf[(kEe * RT + J) * 4 + g], We = cf[(kWe * RT + J) * 4 + g];
             const uint32_t ch = after(chain, ii ? Ro[ii - 1][3] : (la.nonlinear ? gdep : Re[0][0]));
             float z[8];
-            normals4_f32(noise_bits(la.seed, (uint32_t)(8 * J + 2 * g), ch, k, (uint32_t)alpha,
+            scaled_normals4_f32(noise_bits(la.seed, (uint32_t)(8 * J + 2 * g), ch, k, (uint32_t)alpha,
                                     kTagMode),
                          z);
             const float zn = __shfl(z[0], (lane + 16) & 63, 64);
             if (lane < 16) cz[J * 16 + lane] = z[0];
-            normals4_f32(noise_bits(la.seed, (uint32_t)(8 * J + 2 * g + 1), ch, k,
+            scaled_normals4_f32(noise_bits(la.seed, (uint32_t)(8 * J + 2 * g + 1), ch, k,
                                     (uint32_t)alpha, kTagMode),
                          z + 4);
             f32x4 ao, ae;
@@ -1706,23 +1706,24 @@ hipError_t fused_set_coefs(FusedBucket &f, const ModeCoefs &mc, int M, double li
     const int RT = f.RT, Hp = 16 * RT;
     // [kind][slot j]: odd p = 2j + 1, even p = 2j + 2 (scaled by sigma_p);
     // padding p >= M stays zero.  C of the odd modes goes into the table.
+    // W (and W0) carry kNormalScale: the kernels' normals come divided by it.
     std::vector<float> h((size_t)kKinds * Hp, 0.0f);
     for (int j = 0; j < Hp; ++j) {
         const int po = 2 * j + 1, pe = 2 * j + 2;
         if (po < M) {
             h[kEo * Hp + j] = (float)mc.E[po];
-            h[kWo * Hp + j] = (float)mc.W[po];
+            h[kWo * Hp + j] = (float)(kNormalScale * mc.W[po]);
             h[kGo * Hp + j] = (float)(gdt * mc.E[po]);
         }
         if (pe < M) {
             const double sg = f.sig[j];
             h[kEe * Hp + j] = (float)mc.E[pe];
-            h[kWe * Hp + j] = (float)(sg * mc.W[pe]);
+            h[kWe * Hp + j] = (float)(kNormalScale * sg * mc.W[pe]);
             h[kGe * Hp + j] = (float)(gdt * mc.E[pe]);
             h[kCe * Hp + j] = (float)(sg * sg * mc.C[pe]);
         }
     }
-    f.W0 = mc.W[0];
+    f.W0 = kNormalScale * mc.W[0];
     f.gdt = gdt;
     f.lin = (float)lin;
     // Coupling rows whose kick is below FP32 resolution of the update are

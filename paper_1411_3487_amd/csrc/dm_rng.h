@@ -98,22 +98,30 @@ __host__ __device__ __forceinline__ void normals4_f64(const Block4 &b, double z[
     normal_pair_f64(b, 1, z + 2);
 }
 
+// Box-Muller radius factor that the FP32 form leaves to its callers:
+// sqrt(-2 ln u) = sqrt(2 ln 2) sqrt(-log2 u).
+constexpr double kNormalScale = 1.1774100225154747;  // sqrt(2 ln 2)
+
 #if defined(__HIP_DEVICE_COMPILE__) || defined(__HIPCC__)
-// Four N(0,1) in FP32 from the same bits, with the hardware transcendentals:
-// uniforms (x + 1/2) 2^-32 as in FP64, from x rounded to 24 significant bits
-// (never 0; 1 where x rounds to 2^32, which gives the normal 0),
-// v_log_f32 (log2), v_sqrt_f32, and v_sin/v_cos_f32, which take their
-// argument in revolutions, so sin(2 pi u) = sin_rev(u).
-__device__ __forceinline__ void normals4_f32(const Block4 &b, float z[4])
+// Four N(0,1) in FP32 from the same bits, divided by kNormalScale (the caller
+// folds the factor into the coefficient it multiplies them by), with the
+// hardware transcendentals.  Radius: the uniform (x + 1/2) 2^-32 as in FP64,
+// from x rounded to 24 significant bits (never 0; 1 where x rounds to 2^32,
+// which gives the normal 0), v_log_f32 (log2) and v_sqrt_f32 of its
+// negation.  Angle: v_sin/v_cos_f32 take their argument in revolutions and
+// are periodic in it, so the uniform enters as 1 + (x >> 9) 2^-23 in [1, 2),
+// its 23 leading bits placed in a mantissa by one bit alignment (an angle
+// within 2^-23 of a revolution of the FP64 one).
+__device__ __forceinline__ void scaled_normals4_f32(const Block4 &b, float z[4])
 {
-    const float m2ln2 = -1.3862943611198906f;          // -2 ln 2
     const float s32 = 2.3283064365386962890625e-10f;  // 2^-32
     const float u0 = __builtin_fmaf((float)b.v[0], s32, 0.5f * s32);
-    const float u1 = __builtin_fmaf((float)b.v[1], s32, 0.5f * s32);
     const float u2 = __builtin_fmaf((float)b.v[2], s32, 0.5f * s32);
-    const float u3 = __builtin_fmaf((float)b.v[3], s32, 0.5f * s32);
-    const float ra = __builtin_amdgcn_sqrtf(m2ln2 * __builtin_amdgcn_logf(u0));
-    const float rb = __builtin_amdgcn_sqrtf(m2ln2 * __builtin_amdgcn_logf(u2));
+    // {0x7f, x} >> 9: the exponent of 1.0 above the top 23 bits of x
+    const float u1 = __uint_as_float(__builtin_amdgcn_alignbit(0x7fu, b.v[1], 9u));
+    const float u3 = __uint_as_float(__builtin_amdgcn_alignbit(0x7fu, b.v[3], 9u));
+    const float ra = __builtin_amdgcn_sqrtf(-__builtin_amdgcn_logf(u0));
+    const float rb = __builtin_amdgcn_sqrtf(-__builtin_amdgcn_logf(u2));
     z[0] = ra * __builtin_amdgcn_cosf(u1);
     z[1] = ra * __builtin_amdgcn_sinf(u1);
     z[2] = rb * __builtin_amdgcn_cosf(u3);
