@@ -932,9 +932,10 @@ def main():
                    tiles_per_wg=int(tiling["tpw"]), table_mode=shape)
     k_launch = se if se > 0 else 100
     # launch durations settle over the first ~20 launches after the
-    # autotuner (about 830 -> 750 us at 4096 x 256): 20 untimed launches back
-    # to back, then the median of 9 timed ones
-    ctx.step_modes(20 * k_launch)
+    # autotuner (about 830 -> 750 us at 4096 x 256): 20 untimed launches of
+    # the same shape back to back, then the median of 9 timed ones
+    for _ in range(20):
+        ctx.step_modes(k_launch)
     kern = sorted(time_steps(ctx, torch, k_launch, stream) for _ in range(9))[4]
     ctx.close()
 
